@@ -1,0 +1,191 @@
+"""ddLPB oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes front-end of ``libddlpb_oracle.so`` (built from ``ddlpb_oracle.cpp`` by
+``oracle.build()``): a plain FP64 CPU implementation of the discrete ddLPB
+energy, adjoint solve and analytical forces with direct O(M^2) summation.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP product
+path; the Lebedev rule it uses comes straight from SciPy's ``lebedev_rule``
+(a library primitive), independent of the table compiled into the product.
+
+Functions with no independent pin are marked "parity unpinned" in their
+docstring; every other function is pinned by a test in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ddlpb_oracle.cpp")
+_LIB = os.path.join(_HERE, "libddlpb_oracle.so")
+
+# Lebedev rules by point count -> quadrature degree (SciPy's lebedev_rule orders)
+LEBEDEV_DEGREE = {6: 3, 14: 5, 26: 7, 38: 9, 50: 11, 74: 13, 86: 15, 110: 17, 146: 19,
+                  170: 21, 194: 23, 230: 25, 266: 27, 302: 29, 350: 31, 434: 35,
+                  590: 41, 770: 47, 974: 53}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle shared library with g++ (FP64, OpenMP)."""
+    cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-shared", "-fPIC", "-o", _LIB, _SRC]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+def lebedev(n_points: int):
+    """Lebedev points s_n [N,3] and weights w_n [N] with sum w = 4 pi (SciPy)."""
+    from scipy.integrate import lebedev_rule
+    x, w = lebedev_rule(LEBEDEV_DEGREE[n_points])
+    s = np.ascontiguousarray(x.T, dtype=np.float64)
+    assert s.shape[0] == n_points
+    return s, np.ascontiguousarray(w, dtype=np.float64)
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Problem:
+    """Inputs of one ddLPB evaluation (FP64 copies owned by this object)."""
+
+    def __init__(self, centers, radii, charges, eps_in=1.0, eps_out=78.54, kappa=0.104,
+                 lmax=6, n_lebedev=110, eta=0.1, s=None, w=None):
+        self.x = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        self.r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        self.q = np.ascontiguousarray(charges, dtype=np.float64).ravel()
+        self.M = self.x.shape[0]
+        self.eps1, self.eps2, self.kappa, self.eta = float(eps_in), float(eps_out), float(kappa), float(eta)
+        self.lmax = int(lmax)
+        self.L = (self.lmax + 1) ** 2
+        if s is None:
+            s, w = lebedev(n_lebedev)
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.N = self.s.shape[0]
+
+    def _args(self):
+        return (ctypes.c_int(self.M), _ptr(self.x), _ptr(self.r), _ptr(self.q),
+                ctypes.c_double(self.eps1), ctypes.c_double(self.eps2), ctypes.c_double(self.kappa),
+                ctypes.c_double(self.eta), ctypes.c_int(self.lmax), ctypes.c_int(self.N),
+                _ptr(self.s), _ptr(self.w))
+
+    # ---------------------------------------------------------------- pieces
+    def sphere_constants(self):
+        """C_l^j (Sec. 2.2, C1/C2 definition) and i_l'(r_j)/i_l(r_j) (d/dr), each [M, lmax+1]."""
+        out = np.zeros((2, self.M, self.lmax + 1))
+        _load().oracle_sphere_constants(*self._args(), _ptr(out))
+        return out[0], out[1]
+
+    def grid_fields(self):
+        """f^i and chi^eta_i at every grid point x_i^n (Sec. 3.1), each [M, N]; neighbour counts [M]."""
+        f = np.zeros((self.M, self.N))
+        U = np.zeros((self.M, self.N))
+        nn = np.zeros(self.M, dtype=np.int32)
+        _load().oracle_grid_fields(*self._args(), _ptr(f), _ptr(U), nn.ctypes.data_as(_ip))
+        return f, U, nn
+
+    def rhs(self):
+        """g = (G0 + F0, F0) (Sec. 2.2), [2, M, L]."""
+        g = np.zeros((2, self.M, self.L))
+        _load().oracle_rhs(*self._args(), _ptr(g))
+        return g
+
+    def apply(self, X, transpose=False):
+        """L X or L^T X (matrix-free, Sec. 2.2 and the adjoint system of Sec. 3)."""
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(2, self.M, self.L)
+        Y = np.zeros_like(X)
+        _load().oracle_apply(*self._args(), ctypes.c_int(1 if transpose else 0), _ptr(X), _ptr(Y))
+        return Y
+
+    def dense(self):
+        """Literal assembly of L [(2ML)^2] and g [2ML] from the matrix definitions."""
+        D = 2 * self.M * self.L
+        Lm = np.zeros((D, D))
+        g = np.zeros(D)
+        _load().oracle_dense(*self._args(), _ptr(Lm), _ptr(g))
+        return Lm, g
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, method="auto", tol=1e-12, restart=200, maxit=2000, forces=True):
+        """Energy, X, X_adj and forces F = -grad E (e^2/A units).
+
+        method "dense" = LU of the literal matrix; "gmres" = matrix-free GMRES.
+        """
+        if method == "auto":
+            method = "dense" if 2 * self.M * self.L <= 4000 else "gmres"
+        D = 2 * self.M * self.L
+        X = np.zeros(D)
+        Xa = np.zeros(D)
+        F = np.zeros((self.M, 3))
+        E = ctypes.c_double(0.0)
+        info = np.zeros(2, dtype=np.int32)
+        rc = _load().oracle_solve(*self._args(), ctypes.c_int(0 if method == "dense" else 1),
+                                  ctypes.c_double(tol), ctypes.c_int(restart), ctypes.c_int(maxit),
+                                  ctypes.byref(E), _ptr(X), _ptr(Xa), _ptr(F) if forces else None,
+                                  info.ctypes.data_as(_ip))
+        if rc != 0:
+            raise RuntimeError(f"oracle solve failed (rc={rc})")
+        return dict(energy=E.value, X=X.reshape(2, self.M, self.L), Xadj=Xa.reshape(2, self.M, self.L),
+                    forces=F if forces else None, iters=tuple(int(v) for v in info))
+
+    def forces_from(self, X, Xadj):
+        """Forces from given X and X_adj (Sec. 3 force equation)."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        Xa = np.ascontiguousarray(Xadj, dtype=np.float64)
+        F = np.zeros((self.M, 3))
+        _load().oracle_forces_from(*self._args(), _ptr(X), _ptr(Xa), _ptr(F))
+        return F
+
+    def energy_complex_step(self, atom, coord, h=1e-30):
+        """dE/dx_{atom,coord} by the complex step Im E(x + i h e)/h (dense path)."""
+        d = ctypes.c_double(0.0)
+        rc = _load().oracle_energy_cs(*self._args(), ctypes.c_int(atom), ctypes.c_int(coord),
+                                      ctypes.c_double(h), ctypes.byref(d))
+        if rc != 0:
+            raise RuntimeError("complex-step solve failed")
+        return d.value
+
+
+# ------------------------------------------------------------ table routines
+def sph_harm(lmax, v):
+    """Real orthonormal Y_lm(v/|v|), [n, (lmax+1)^2], index l*l+l+m."""
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((v.shape[0], (lmax + 1) ** 2))
+    _load().oracle_sph_harm(ctypes.c_int(lmax), ctypes.c_int(v.shape[0]), _ptr(v), _ptr(out))
+    return out
+
+
+def bessel(lmax, z):
+    """(i_l, k_l, i_l', k_l') at z for l = 0..lmax, each [lmax+1]."""
+    out = np.zeros((4, lmax + 1))
+    _load().oracle_bessel(ctypes.c_int(lmax), ctypes.c_double(z), _ptr(out))
+    return out
+
+
+def switch(eta, t):
+    """(chi_eta(t), chi_eta'(t)) (Sec. 3.1 regularised characteristic function)."""
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    out = np.zeros((2, t.size))
+    _load().oracle_switch(ctypes.c_double(eta), ctypes.c_int(t.size), _ptr(t), _ptr(out))
+    return out[0], out[1]
