@@ -1,0 +1,172 @@
+/*
+ * ddlpb.h -- C ABI of the MI355X (gfx950) ddLPB library.
+ *
+ * The library computes the discrete ddLPB electrostatic solvation energy of a
+ * union of atomic spheres, its adjoint solution and the analytical solvation
+ * forces (Jha, Nottoli, Mikhalev, Quan, Stamm: "Linear scaling computation of
+ * forces for the domain-decomposition linear Poisson--Boltzmann method").
+ * Every numerical step runs in HIP kernels on the current GPU.
+ *
+ * Problem statement (Sec. 1 and Sec. 2.1): point charges q_j at the centres
+ * x_j of balls of radius r_j; permittivity eps_in inside the union of balls,
+ * eps_out and Debye--Hueckel screening constant kappa outside.  Discretisation
+ * (Sec. 2.2): real spherical harmonics up to degree lmax on every sphere and
+ * a Lebedev rule with n_lebedev points.  Units: Angstrom, elementary charge;
+ * energies in e^2/Angstrom, forces in e^2/Angstrom^2 (Coulomb constant 1).
+ *
+ * Conventions common to every call:
+ *   - Return value 0 = success, a negative DDLPB_E* code on error.  No C++
+ *     exception crosses the boundary.  On error, outputs are left unwritten.
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     copies what it needs before returning.  Results are on the host when a
+ *     call returns.
+ *   - A context is used by one host thread at a time; different contexts are
+ *     independent (no global mutable state besides per-device constant tables).
+ */
+#ifndef DDLPB_H
+#define DDLPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define DDLPB_OK 0
+#define DDLPB_EINVAL (-1)   /* invalid argument (sizes, non-finite values, unsupported grid) */
+#define DDLPB_EGEOM (-2)    /* coincident sphere centres (distance < 1e-12 A) */
+#define DDLPB_ENOMEM (-3)   /* device or host allocation failed / workspace too small */
+#define DDLPB_EDEVICE (-4)  /* a HIP call failed */
+#define DDLPB_ENOCONV (-5)  /* iterative solver did not reach the tolerance in max_iter */
+#define DDLPB_ESTATE (-6)   /* call order violated (e.g. forces before adjoint) */
+
+typedef struct ddlpb_ctx ddlpb_ctx;
+
+/* Per-solve statistics (ddlpb_get_stats). */
+typedef struct {
+  int32_t iters_primal;      /* GMRES iterations of the last primal solve */
+  int32_t iters_adjoint;     /* GMRES iterations of the last adjoint solve */
+  double resid_primal;       /* final relative residual ||g - L X|| / ||g|| */
+  double resid_adjoint;      /* final relative residual ||Q - L^T X_adj|| / ||Q|| */
+  double ms_setup;           /* device setup (grid fields, tables, tree) */
+  double ms_rhs;             /* right-hand side g */
+  double ms_primal;          /* primal solve */
+  double ms_adjoint;         /* adjoint solve */
+  double ms_forces;          /* force assembly */
+  int64_t n_cap_pairs;       /* (i, n, j) triples with omega_ij(x_i^n) > 0 */
+  int64_t n_active_points;   /* grid points with chi^eta_i(x_i^n) > 0 */
+  int64_t n_near_pairs;      /* sphere pairs evaluated directly in the single layer */
+  int64_t n_m2l;             /* multipole-to-local translations per field evaluation */
+  int32_t fmm_order;         /* 0 = direct summation */
+  int32_t precision;         /* 0 = FP64, 1 = mixed */
+  int32_t refinements;       /* FP64 refinement steps of the mixed path */
+  int32_t fmm_order_below_lmax; /* 1 if 0 < fmm_order < lmax (forces inaccurate, Sec. 4.1.2) */
+} ddlpb_stats;
+
+/*
+ * ddlpb_setup -- validate inputs, copy them and analyse the geometry.
+ *   n_atoms     M >= 1
+ *   centers     [M][3] row-major, host, Angstrom
+ *   radii       [M] host, Angstrom, > 0
+ *   charges     [M] host, e
+ *   eps_in, eps_out > 0; kappa > 0 (1/Angstrom)
+ *   lmax        0..10, maximal harmonic degree on every sphere (Sec. 2.2)
+ *   n_lebedev   one of 6, 14, 26, 38, 50, 74, 86, 110, 146, 170, 194, 230, 266, 302,
+ *               350, 434, 590, 770, 974 and of quadrature degree >= 2*lmax
+ *   fmm_order   0 = direct O(M^2) single layer and vacuum field;
+ *               p > 0 = fast multipole method of order p (Appendix)
+ *   out         receives the new context
+ * Defaults (change with ddlpb_set_option before the first solve): eta = 0.1,
+ * FP64, GMRES restart 40, 8 Jacobi sweeps, max_iter 500, leaf size 32.
+ * Errors: EINVAL, EGEOM, ENOMEM.  Device memory is allocated lazily at the
+ * first solve unless a workspace is bound.
+ */
+int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, const double* charges,
+                double eps_in, double eps_out, double kappa, int32_t lmax, int32_t n_lebedev,
+                int32_t fmm_order, ddlpb_ctx** out);
+
+/*
+ * ddlpb_solve -- primal solve L X = g (Sec. 2.2 block system) to relative
+ * residual tol, then the energy E_s = 1/2 sum_j q_j psi_r(x_j) (Sec. 3 energy
+ * equation), written to *energy_out (host, e^2/Angstrom).
+ * Errors: ENOCONV (best iterate kept, energy written), EDEVICE, ENOMEM.
+ */
+int ddlpb_solve(ddlpb_ctx* ctx, double tol, double* energy_out);
+
+/*
+ * ddlpb_adjoint -- adjoint solve L^T X_adj = Q (Sec. 3 adjoint system) to
+ * relative residual tol.  Requires a prior ddlpb_solve (else ESTATE).
+ */
+int ddlpb_adjoint(ddlpb_ctx* ctx, double tol);
+
+/*
+ * ddlpb_forces -- analytical forces F = -grad_{x_k} E_s (Sec. 3.1, contracted
+ * with X_adj as in the Sec. 3 force equation), written to forces_out [M][3]
+ * (host, e^2/Angstrom^2).  Requires a prior ddlpb_adjoint (else ESTATE).
+ */
+int ddlpb_forces(ddlpb_ctx* ctx, double* forces_out);
+
+/* ddlpb_free -- release the context and any device memory it allocated. NULL is a no-op. */
+void ddlpb_free(ddlpb_ctx* ctx);
+
+/*
+ * ddlpb_set_option -- set a tuning option before the first solve (else ESTATE
+ * for options that change the discrete problem: eta, precision, fmm_order).
+ *   "eta"            switching width of chi_eta (Sec. 3.1), 0 < eta <= 1
+ *   "precision"      0 = FP64 everywhere, 1 = mixed (FP32 matvec kernels, FP64
+ *                    Krylov/reductions/Bessel ratios, FP64 outer refinement)
+ *   "gmres_restart"  Krylov subspace size (1..200)
+ *   "inner_sweeps"   Jacobi sweeps of the L_AB preconditioner (0..64)
+ *   "max_iter"       maximal GMRES iterations per solve
+ *   "leaf_size"      maximal spheres per FMM tree leaf
+ *   "theta"          FMM acceptance parameter (0 < theta < 1)
+ * Errors: EINVAL (unknown key or value out of range), ESTATE.
+ */
+int ddlpb_set_option(ddlpb_ctx* ctx, const char* key, double value);
+
+/*
+ * ddlpb_update_centers -- new conformation of the same molecule (same radii,
+ * charges and parameters); [M][3] host.  X and X_adj are kept as initial
+ * guesses of the next solves.  Errors: EINVAL, EGEOM.
+ */
+int ddlpb_update_centers(ddlpb_ctx* ctx, const double* centers);
+
+/*
+ * Device memory and stream binding (lets a framework such as PyTorch own them).
+ * ddlpb_workspace_bytes: bytes of device memory the context needs for its
+ *   current geometry and options (also the HBM footprint used for admission).
+ * ddlpb_bind_workspace: use [dev, dev+bytes) (device pointer, 256-byte aligned)
+ *   instead of allocating; the caller keeps it alive until ddlpb_free or the
+ *   next bind.  ENOMEM if bytes < ddlpb_workspace_bytes.
+ * ddlpb_set_stream: enqueue all work on this hipStream_t (NULL = default stream).
+ */
+size_t ddlpb_workspace_bytes(const ddlpb_ctx* ctx);
+int ddlpb_bind_workspace(ddlpb_ctx* ctx, void* dev, size_t bytes);
+int ddlpb_set_stream(ddlpb_ctx* ctx, void* hip_stream);
+
+/* ddlpb_get_stats -- copy the statistics of the last calls. */
+int ddlpb_get_stats(const ddlpb_ctx* ctx, ddlpb_stats* out);
+
+/* ddlpb_strerror -- static description of an error code. */
+const char* ddlpb_strerror(int code);
+
+/*
+ * Inspection entry points (tests and diagnostics).  All buffers are host memory.
+ * ddlpb_get_grid:     f^i(x_i^n) and chi^eta_i(x_i^n) (Sec. 3.1), each [M][N].
+ * ddlpb_get_solution: X and X_adj (Sec. 2.2 and Sec. 3), each [2][M][L],
+ *                     L = (lmax+1)^2, index l*l+l+m; either may be NULL.
+ * ddlpb_get_rhs:      g = (G0 + F0, F0) (Sec. 2.2), [2][M][L].
+ * ddlpb_apply:        Y = L X (transpose 0) or L^T X (transpose 1) with the
+ *                     context's operators (FMM if fmm_order > 0), [2][M][L].
+ */
+int ddlpb_get_grid(ddlpb_ctx* ctx, double* f_out, double* u_out);
+int ddlpb_get_solution(ddlpb_ctx* ctx, double* x_out, double* xadj_out);
+int ddlpb_get_rhs(ddlpb_ctx* ctx, double* g_out);
+int ddlpb_apply(ddlpb_ctx* ctx, int32_t transpose, const double* x_in, double* y_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDLPB_H */

@@ -1,0 +1,180 @@
+// Device-side special functions for the ddLPB kernels (gfx950).
+//
+//  * Regular solid harmonics S_lm(v) = |v|^l Y_lm(v/|v|) of the real orthonormal
+//    spherical harmonics (Y_{l,m} ~ cos(m phi) for m > 0, ~ sin(|m| phi) for m < 0,
+//    no Condon-Shortley sign, index l*l+l+m), evaluated by a recurrence in
+//    Cartesian form so that no direction has to be normalised (a grid point
+//    close to another sphere's centre is harmless).
+//  * Radial weights of the modified spherical Bessel functions:
+//      k-weights  u_l(rho) = k_l(kappa rho) / rho^l   (upward recurrence, stable)
+//      i-weights  sigma_l(z^2) = i_l(z) / z^l        (series at the top, downward
+//                                                      recurrence, stable)
+//  * A forward-mode dual number (value + gradient) for gradients with respect to
+//    an evaluation point.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ddlpb {
+
+constexpr int kLmaxDev = 24;                          // largest degree of the constant tables
+constexpr int kTri = (kLmaxDev + 1) * (kLmaxDev + 2) / 2;
+__host__ __device__ constexpr int tri(int l, int m) { return l * (l + 1) / 2 + m; }
+__host__ __device__ constexpr int lmi(int l, int m) { return l * l + l + m; }
+
+// Normalised Legendre recurrence constants (filled by the host once per device):
+//   P_m^m = c_pmm[m],  P_{m+1}^m = c_ra[tri(m+1,m)] z P_m^m,
+//   P_l^m = c_ra[tri(l,m)] z P_{l-1}^m - c_rb[tri(l,m)] r^2 P_{l-2}^m
+// where P_l^m already carries the normalisation of Y_lm.
+__constant__ double c_pmm[kLmaxDev + 1];
+__constant__ double c_ra[kTri];
+__constant__ double c_rb[kTri];
+
+// ------------------------------------------------------------------ dual
+template <class R>
+struct Dual {
+  R v, g[3];
+  __device__ Dual() {}
+  __device__ Dual(R a) : v(a) { g[0] = g[1] = g[2] = R(0); }
+};
+template <class R> __device__ __forceinline__ Dual<R> operator+(const Dual<R>& a, const Dual<R>& b) { Dual<R> r; r.v = a.v + b.v; for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] + b.g[k]; return r; }
+template <class R> __device__ __forceinline__ Dual<R> operator-(const Dual<R>& a, const Dual<R>& b) { Dual<R> r; r.v = a.v - b.v; for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] - b.g[k]; return r; }
+template <class R> __device__ __forceinline__ Dual<R> operator*(const Dual<R>& a, const Dual<R>& b) { Dual<R> r; r.v = a.v * b.v; for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * b.v + a.v * b.g[k]; return r; }
+template <class R> __device__ __forceinline__ Dual<R> operator*(R s, const Dual<R>& a) { Dual<R> r; r.v = s * a.v; for (int k = 0; k < 3; ++k) r.g[k] = s * a.g[k]; return r; }
+template <class R> __device__ __forceinline__ Dual<R> operator*(const Dual<R>& a, R s) { return s * a; }
+template <class R> __device__ __forceinline__ Dual<R> operator/(const Dual<R>& a, const Dual<R>& b) {
+  Dual<R> r; R ib = R(1) / b.v; r.v = a.v * ib;
+  for (int k = 0; k < 3; ++k) r.g[k] = (a.g[k] - r.v * b.g[k]) * ib;
+  return r;
+}
+template <class R> __device__ __forceinline__ Dual<R> dsqrt(const Dual<R>& a) {
+  Dual<R> r; r.v = sqrt(a.v); R h = R(0.5) / r.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * h;
+  return r;
+}
+template <class R> __device__ __forceinline__ Dual<R> dexp(const Dual<R>& a) {
+  Dual<R> r; r.v = exp(a.v);
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * r.v;
+  return r;
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float dsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double dexp(double a) { return exp(a); }
+__device__ __forceinline__ float dexp(float a) { return expf(a); }
+
+template <class T> struct ScalarOf { using type = T; };
+template <class R> struct ScalarOf<Dual<R>> { using type = R; };
+
+// ---------------------------------------------------- solid harmonics
+// Calls f(l, m_index, S_lm) for every (l,m), l <= LM, in the order m = 0..LM, l = m..LM.
+// T may be a scalar or a Dual (then S carries its gradient w.r.t. (x,y,z)).
+template <int LM, class T, class F>
+__device__ __forceinline__ void for_each_solid_harmonic(const T& x, const T& y, const T& z, F&& f) {
+  using R = typename ScalarOf<T>::type;
+  const T r2 = x * x + y * y + z * z;
+  T cm(R(1)), sm(R(0));
+#pragma unroll
+  for (int m = 0; m <= LM; ++m) {
+    if (m > 0) {
+      T c2 = x * cm - y * sm;
+      sm = x * sm + y * cm;
+      cm = c2;
+    }
+    T p2(R(0)), p1(R(0));
+#pragma unroll
+    for (int l = m; l <= LM; ++l) {
+      T p;
+      if (l == m) p = T(R(c_pmm[m]));
+      else if (l == m + 1) p = R(c_ra[tri(l, m)]) * (z * p1);
+      else p = R(c_ra[tri(l, m)]) * (z * p1) - R(c_rb[tri(l, m)]) * (r2 * p2);
+      if (m == 0) {
+        f(l, lmi(l, 0), p);
+      } else {
+        f(l, lmi(l, m), p * cm);
+        f(l, lmi(l, -m), p * sm);
+      }
+      p2 = p1;
+      p1 = p;
+    }
+  }
+}
+
+// ------------------------------------------------------ Bessel weights
+// u_l = k_l(kappa rho) / rho^l for l = 0..LM (k_l = sqrt(pi/(2z)) K_{l+1/2}(z)).
+template <int LM, class T>
+__device__ __forceinline__ void k_weights(const T& rho, double kappa, T* u) {
+  using R = typename ScalarOf<T>::type;
+  const R halfpi = R(1.5707963267948966);
+  T z = R(kappa) * rho;
+  T e = dexp(T(R(0)) - z);
+  u[0] = halfpi * (e / z);
+  if (LM >= 1) u[1] = halfpi * (e * (z + T(R(1)))) / (z * z * rho);
+  T ir2 = T(R(1)) / (rho * rho);
+#pragma unroll
+  for (int l = 1; l < LM; ++l) u[l + 1] = (u[l - 1] + R((2.0 * l + 1.0) / kappa) * u[l]) * ir2;
+}
+template <class R> __device__ __forceinline__ Dual<R> operator+(const Dual<R>& a, R s) { Dual<R> r = a; r.v += s; return r; }
+
+// sigma_l(z2) = i_l(z)/z^l, l = 0..LM: series for LM+1 and LM, then
+// sigma_{l-1} = z2 sigma_{l+1} + (2l+1) sigma_l.
+template <int LM, class T>
+__device__ __forceinline__ void sigma_weights(const T& z2, int nterms, T* sg) {
+  using R = typename ScalarOf<T>::type;
+  T top[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int l = LM + 1 - q;
+    double df = 1.0;
+    for (int k = 2 * l + 1; k > 1; k -= 2) df *= k;
+    T term = T(R(1.0 / df));
+    T sum = term;
+    for (int k = 0; k < nterms; ++k) {
+      term = (term * z2) * R(0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0)));
+      sum = sum + term;
+    }
+    top[q] = sum;
+  }
+  T sp1 = top[0];
+  sg[LM] = top[1];
+#pragma unroll
+  for (int l = LM; l >= 1; --l) {
+    T s = z2 * sp1 + R(2.0 * l + 1.0) * sg[l];
+    sp1 = sg[l];
+    sg[l - 1] = s;
+  }
+}
+
+// ------------------------------------------------------------ switching
+// chi_eta(t): 1 for t <= 1-eta, 0 for t >= 1, C^2 quintic in between; and its derivative.
+__device__ __forceinline__ double chi_eta(double t, double eta) {
+  if (t <= 1.0 - eta) return 1.0;
+  if (t >= 1.0) return 0.0;
+  double u = (1.0 - t) / eta;
+  return u * u * u * (u * (6.0 * u - 15.0) + 10.0);
+}
+__device__ __forceinline__ double chi_eta_d(double t, double eta) {
+  if (t <= 1.0 - eta || t >= 1.0) return 0.0;
+  double u = (1.0 - t) / eta;
+  return -30.0 * u * u * (u - 1.0) * (u - 1.0) / eta;
+}
+
+// -------------------------------------------------------- reductions
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+// Deterministic block sum (blockDim.x multiple of 64, <= 1024); result valid in all threads.
+template <class R>
+__device__ __forceinline__ R block_sum(R v, R* sh /* >= 16 entries */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  R t = R(0);
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  return t;
+}
+
+}  // namespace ddlpb

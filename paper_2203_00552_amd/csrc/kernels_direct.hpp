@@ -1,0 +1,533 @@
+// ddLPB kernels for gfx950: grid switching fields, per-sphere harmonic
+// transforms, the sparse neighbour-sphere A/B operators (and transposes), the
+// single-layer (screened Coulomb) field by direct summation and its adjoint,
+// the vacuum Coulomb field, Krylov helpers and the force assembly.
+//
+// Layouts (all FP64, row-major):
+//   centres xyz [M][3], radii [M], charges [M]
+//   Lebedev rule leb [N][4] = (s_x, s_y, s_z, w)
+//   Y table [N][LY]  (Y_lm(s_n), index l*l+l+m)
+//   grid functions [M][N]; harmonic vectors [M][L] and solution vectors [2][M][L]
+//   per-sphere radial tables [M][LUR] (LUR = lmax+2)
+//   active points: the grid points with chi^eta > 0, listed sphere by sphere
+//   (act_sph[k], act_n[k]), act_ptr[M+1].
+#pragma once
+#include <type_traits>
+
+#include "device_math.hpp"
+
+namespace ddlpb {
+
+constexpr int kMaxN = 974;
+
+__device__ __forceinline__ int deg_of(int lm) {
+  int l = (int)sqrt((double)lm);
+  while ((l + 1) * (l + 1) <= lm) ++l;
+  while (l * l > lm) --l;
+  return l;
+}
+
+// ------------------------------------------------------------- grid fields
+// f^i(x_i^n) = sum_{j in N_i} chi_eta(|x_i^n - x_j| / r_j),  U = 1 - min(f, 1)   (Sec. 3.1)
+__global__ void k_grid_fields(int M, int N, const double* __restrict__ xyz, const double* __restrict__ rad,
+                              const double* __restrict__ leb, const int* __restrict__ nptr,
+                              const int* __restrict__ nidx, double eta, double* __restrict__ f,
+                              double* __restrict__ U) {
+  long g = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (g >= (long)M * N) return;
+  int i = (int)(g / N), n = (int)(g - (long)i * N);
+  const double px = xyz[3 * i] + rad[i] * leb[4 * n];
+  const double py = xyz[3 * i + 1] + rad[i] * leb[4 * n + 1];
+  const double pz = xyz[3 * i + 2] + rad[i] * leb[4 * n + 2];
+  double fs = 0.0;
+  for (int a = nptr[i]; a < nptr[i + 1]; ++a) {
+    int j = nidx[a];
+    double dx = px - xyz[3 * j], dy = py - xyz[3 * j + 1], dz = pz - xyz[3 * j + 2];
+    fs += chi_eta(sqrt(dx * dx + dy * dy + dz * dz) / rad[j], eta);
+  }
+  f[g] = fs;
+  U[g] = fs < 1.0 ? 1.0 - fs : 0.0;
+}
+
+// number of active points (U > 0) and cap pairs (omega > 0) per sphere
+__global__ void k_active_count(int M, int N, const double* __restrict__ U, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int c = 0;
+  for (int n = 0; n < N; ++n) c += U[(long)i * N + n] > 0.0;
+  cnt[i] = c;
+}
+__global__ void k_active_fill(int M, int N, const double* __restrict__ U, const int* __restrict__ ptr,
+                              int* __restrict__ act_sph, int* __restrict__ act_n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int k = ptr[i];
+  for (int n = 0; n < N; ++n)
+    if (U[(long)i * N + n] > 0.0) { act_sph[k] = i; act_n[k] = n; ++k; }
+}
+
+__global__ void k_fill(long n, double v, double* __restrict__ a) {
+  long g = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (g < n) a[g] = v;
+}
+
+// ----------------------------------------------------- single-layer moments
+// m_j = C^j (.) An_j(U_j (.) (e_j + Syn(y_j))), y_j = ycr_l X_r,j + yce_l X_e,j  (Sec. 2.2, Q and P chi)
+// Optionally stores h = e + Syn(y) on the grid.
+template <int LM>
+__global__ __launch_bounds__(256) void k_moments(int M, int N, int LY, const double* __restrict__ Y,
+                                                  const double* __restrict__ leb, const double* __restrict__ U,
+                                                  const double* __restrict__ X, const double* __restrict__ ycr,
+                                                  const double* __restrict__ yce, int LUR,
+                                                  const double* __restrict__ egrid, const double* __restrict__ Cl,
+                                                  double* __restrict__ h_out, double* __restrict__ m_out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double y[L];
+  __shared__ double hu[kMaxN];
+  const int j = blockIdx.x;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double v = 0.0;
+    if (X) {
+      int l = deg_of(t);
+      v = ycr[j * LUR + l] * X[(long)j * L + t] + yce[j * LUR + l] * X[(long)(M + j) * L + t];
+    }
+    y[t] = v;
+  }
+  __syncthreads();
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    double h = egrid ? egrid[(long)j * N + n] : 0.0;
+    if (X) {
+      const double* Yn = Y + (long)n * LY;
+#pragma unroll 9
+      for (int t = 0; t < L; ++t) h += Yn[t] * y[t];
+    }
+    if (h_out) h_out[(long)j * N + n] = h;
+    hu[n] = U[(long)j * N + n] * h;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double acc = 0.0;
+    for (int n = 0; n < N; ++n) acc += leb[4 * n + 3] * Y[(long)n * LY + t] * hu[n];
+    m_out[(long)j * L + t] = Cl[j * LUR + deg_of(t)] * acc;
+  }
+}
+
+// ------------------------------------------------ single-layer field (direct)
+// Phi(x) = sum_j sum_lm m_jlm k_l(kappa|x-x_j|)/k_l(kappa r_j) Y_lm((x-x_j)/|x-x_j|)
+// at every active point, or its gradient with respect to x (GRAD).  One thread
+// per active point, source spheres staged through LDS in chunks.
+template <int LM, bool GRAD>
+__global__ __launch_bounds__(256) void k_sl_field_direct(int M, int N, int nact, const int* __restrict__ act_sph,
+                                                          const int* __restrict__ act_n,
+                                                          const double* __restrict__ xyz,
+                                                          const double* __restrict__ rad,
+                                                          const double* __restrict__ leb,
+                                                          const double* __restrict__ m,
+                                                          const double* __restrict__ ur, int LUR, double kappa,
+                                                          int exclude_self, double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  constexpr int CH = 16;
+  __shared__ double sm[CH * L];
+  __shared__ double sx[CH * 4];
+  __shared__ double sur[CH * (LM + 1)];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = k < nact;
+  const int i = active ? act_sph[k] : -1;
+  const int n = active ? act_n[k] : 0;
+  double p[3] = {0, 0, 0};
+  if (active)
+    for (int a = 0; a < 3; ++a) p[a] = xyz[3 * i + a] + rad[i] * leb[4 * n + a];
+  using T = typename std::conditional<GRAD, Dual<double>, double>::type;
+  T acc(0.0);
+  for (int j0 = 0; j0 < M; j0 += CH) {
+    const int nc = min(CH, M - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) sm[t] = m[(long)j0 * L + t];
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+      const int j = j0 + t;
+      sx[4 * t] = xyz[3 * j]; sx[4 * t + 1] = xyz[3 * j + 1]; sx[4 * t + 2] = xyz[3 * j + 2]; sx[4 * t + 3] = rad[j];
+      for (int l = 0; l <= LM; ++l) sur[t * (LM + 1) + l] = 1.0 / ur[j * LUR + l];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int c = 0; c < nc; ++c) {
+      if (exclude_self && j0 + c == i) continue;
+      const double rj = sx[4 * c + 3], irj = 1.0 / rj;
+      T v[3];
+      for (int a = 0; a < 3; ++a) {
+        v[a] = T(p[a]);
+        if constexpr (GRAD) v[a].g[a] = 1.0;
+        v[a] = (v[a] - T(sx[4 * c + a])) * irj;  // scaled relative position
+      }
+      T rho = dsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * rj;
+      T u[LM + 1];
+      k_weights<LM, T>(rho, kappa, u);
+      const double* mc = sm + c * L;
+      const double* iu = sur + c * (LM + 1);
+      T part[LM + 1];
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) part[l] = T(0.0);
+      for_each_solid_harmonic<LM, T>(v[0], v[1], v[2], [&](int l, int idx, const T& S) { part[l] = part[l] + mc[idx] * S; });
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) acc = acc + (iu[l] * u[l]) * part[l];
+    }
+  }
+  if (!active) return;
+  if constexpr (GRAD) {
+    for (int a = 0; a < 3; ++a) out[3L * k + a] = acc.g[a];
+  } else {
+    out[(long)i * N + n] = acc;
+  }
+}
+
+// -------------------------------------------- single-layer adjoint (direct)
+// lambda_jlm = sum_{(i,n) active} c_in k_l(kappa|x_i^n-x_j|)/k_l(kappa r_j) Y_lm(...), l <= LMO.
+// One block per target sphere j, threads over all active source points,
+// register accumulation and a deterministic block reduction.
+template <int LMO>
+__global__ __launch_bounds__(256) void k_sl_adjoint_direct(int M, int N, int nact, const int* __restrict__ act_sph,
+                                                            const int* __restrict__ act_n,
+                                                            const double* __restrict__ xyz,
+                                                            const double* __restrict__ rad,
+                                                            const double* __restrict__ leb,
+                                                            const double* __restrict__ cgrid,
+                                                            const double* __restrict__ ur, int LUR, double kappa,
+                                                            int exclude_self, double* __restrict__ lam) {
+  constexpr int LO = (LMO + 1) * (LMO + 1);
+  __shared__ double red[4 * LO];
+  const int j = blockIdx.x;
+  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
+  double iu[LMO + 1];
+#pragma unroll
+  for (int l = 0; l <= LMO; ++l) iu[l] = 1.0 / ur[j * LUR + l];
+  double acc[LO];
+#pragma unroll
+  for (int t = 0; t < LO; ++t) acc[t] = 0.0;
+  for (int k = threadIdx.x; k < nact; k += blockDim.x) {
+    const int i = act_sph[k], n = act_n[k];
+    if (exclude_self && i == j) continue;
+    const double c = cgrid[(long)i * N + n];
+    if (c == 0.0) continue;
+    const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+    const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+    const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+    const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
+    double u[LMO + 1];
+    k_weights<LMO, double>(rho, kappa, u);
+#pragma unroll
+    for (int l = 0; l <= LMO; ++l) u[l] *= c * iu[l];
+    for_each_solid_harmonic<LMO, double>(vx, vy, vz, [&](int l, int idx, double S) { acc[idx] += u[l] * S; });
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < LO; ++t) {
+    double v = wave_sum(acc[t]);
+    if (lane == 0) red[wid * LO + t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < LO; t += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * LO + t];
+    lam[(long)j * LO + t] = s;
+  }
+}
+
+// --------------------------------------------------- vacuum field (direct)
+// psi_0(x) = sum_k q_k/(eps1 |x - x_k|) and e = (eps1/eps2) d_n psi_0 at active points (Sec. 2.2, G0, F0).
+__global__ __launch_bounds__(256) void k_laplace_field_direct(int M, int N, int nact, const int* __restrict__ act_sph,
+                                                              const int* __restrict__ act_n,
+                                                              const double* __restrict__ xyz,
+                                                              const double* __restrict__ rad,
+                                                              const double* __restrict__ leb,
+                                                              const double* __restrict__ q, double eps1,
+                                                              double eps2, double* __restrict__ psi_out,
+                                                              double* __restrict__ e_out) {
+  __shared__ double sq[256 * 4];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = k < nact;
+  const int i = active ? act_sph[k] : 0, n = active ? act_n[k] : 0;
+  double p[3], s[3];
+  for (int a = 0; a < 3; ++a) { s[a] = leb[4 * n + a]; p[a] = xyz[3 * i + a] + rad[i] * s[a]; }
+  double psi = 0.0, dn = 0.0;
+  for (int k0 = 0; k0 < M; k0 += 256) {
+    const int nc = min(256, M - k0);
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      const int kk = k0 + threadIdx.x;
+      sq[4 * threadIdx.x] = xyz[3 * kk]; sq[4 * threadIdx.x + 1] = xyz[3 * kk + 1];
+      sq[4 * threadIdx.x + 2] = xyz[3 * kk + 2]; sq[4 * threadIdx.x + 3] = q[kk];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int c = 0; c < nc; ++c) {
+      double vx = p[0] - sq[4 * c], vy = p[1] - sq[4 * c + 1], vz = p[2] - sq[4 * c + 2];
+      double id = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+      double qi = sq[4 * c + 3] * id;
+      psi += qi;
+      dn -= qi * id * id * (vx * s[0] + vy * s[1] + vz * s[2]);
+    }
+  }
+  if (!active) return;
+  psi_out[(long)i * N + n] = psi / eps1;
+  e_out[(long)i * N + n] = dn / eps2;
+}
+
+// ------------------------------------------------------ apply L (near part)
+// out_r = c0 base_r + c1 An(sum_j omega_ij vA_j) + cg An(U (gr1 + gr2))
+// out_e = c0 base_e + c1 An(sum_j omega_ij vB_j) + cg An(U ge)
+// with vA_j(x) = sum_lm X_r,jlm (|x-x_j|/r_j)^l Y_lm, vB_j the same with
+// i_l(kappa|x-x_j|)/i_l(kappa r_j) (Sec. 2.2, A and B).  One block per sphere.
+template <int LM>
+__global__ __launch_bounds__(256) void k_apply_LX(int M, int N, int LY, const double* __restrict__ Y,
+                                                   const double* __restrict__ leb, const double* __restrict__ xyz,
+                                                   const double* __restrict__ rad, const int* __restrict__ nptr,
+                                                   const int* __restrict__ nidx, const double* __restrict__ f,
+                                                   const double* __restrict__ U, const double* __restrict__ sgr,
+                                                   int LUR, double kappa, double eta, int nterms,
+                                                   const double* __restrict__ base, double c0,
+                                                   const double* __restrict__ nearX, double c1,
+                                                   const double* __restrict__ gr1, const double* __restrict__ gr2,
+                                                   const double* __restrict__ ge, double cg,
+                                                   double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double vA[kMaxN], vB[kMaxN], gR[kMaxN], gE[kMaxN];
+  const int i = blockIdx.x;
+  const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2], ri = rad[i];
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    if (nearX) {
+      const double px = xi + ri * leb[4 * n], py = yi + ri * leb[4 * n + 1], pz = zi + ri * leb[4 * n + 2];
+      const double fv = f[(long)i * N + n];
+      const double dfac = fv > 1.0 ? 1.0 / fv : 1.0;
+      for (int q = nptr[i]; q < nptr[i + 1]; ++q) {
+        const int j = nidx[q];
+        const double irj = 1.0 / rad[j];
+        const double vx = (px - xyz[3 * j]) * irj, vy = (py - xyz[3 * j + 1]) * irj, vz = (pz - xyz[3 * j + 2]) * irj;
+        const double t2 = vx * vx + vy * vy + vz * vz;
+        if (t2 >= 1.0) continue;
+        const double om = dfac * chi_eta(sqrt(t2), eta);
+        if (om == 0.0) continue;
+        double sg[LM + 1];
+        sigma_weights<LM, double>(kappa * kappa * rad[j] * rad[j] * t2, nterms, sg);
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) sg[l] /= sgr[j * LUR + l];
+        const double* Xr = nearX + (long)j * L;
+        const double* Xe = nearX + (long)(M + j) * L;
+        double sa = 0.0, pb[LM + 1];
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) pb[l] = 0.0;
+        for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
+          sa += Xr[idx] * S;
+          pb[l] += Xe[idx] * S;
+        });
+        double sb = 0.0;
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) sb += sg[l] * pb[l];
+        a += om * sa;
+        b += om * sb;
+      }
+    }
+    vA[n] = a;
+    vB[n] = b;
+    const double u = U[(long)i * N + n];
+    gR[n] = gr1 ? u * (gr1[(long)i * N + n] + (gr2 ? gr2[(long)i * N + n] : 0.0)) : 0.0;
+    gE[n] = ge ? u * ge[(long)i * N + n] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double sa = 0.0, sb = 0.0, sr = 0.0, se = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double wy = leb[4 * n + 3] * Y[(long)n * LY + t];
+      sa += wy * vA[n];
+      sb += wy * vB[n];
+      sr += wy * gR[n];
+      se += wy * gE[n];
+    }
+    const long ir = (long)i * L + t, ie = (long)(M + i) * L + t;
+    double orr = c1 * sa + cg * sr, oe = c1 * sb + cg * se;
+    if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
+    out[ir] = orr;
+    out[ie] = oe;
+  }
+}
+
+// ---------------------------------------------- syntheses on the grid
+// mode 0: zr = Syn(Z_r), ze = Syn(Z_e);  mode 1: c = w U Syn(Z_r + Z_e) (adjoint charges)
+template <int LM>
+__global__ __launch_bounds__(256) void k_syn2(int M, int N, int LY, const double* __restrict__ Y,
+                                               const double* __restrict__ leb, const double* __restrict__ U,
+                                               const double* __restrict__ Z, int mode, double* __restrict__ o1,
+                                               double* __restrict__ o2) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double zr[L], ze[L];
+  const int i = blockIdx.x;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    zr[t] = Z[(long)i * L + t];
+    ze[t] = Z[(long)(M + i) * L + t];
+  }
+  __syncthreads();
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    const double* Yn = Y + (long)n * LY;
+    double a = 0.0, b = 0.0;
+#pragma unroll 9
+    for (int t = 0; t < L; ++t) { a += Yn[t] * zr[t]; b += Yn[t] * ze[t]; }
+    if (mode == 0) {
+      o1[(long)i * N + n] = a;
+      o2[(long)i * N + n] = b;
+    } else {
+      o1[(long)i * N + n] = leb[4 * n + 3] * U[(long)i * N + n] * (a + b);
+    }
+  }
+}
+
+// ------------------------------------------------------- apply L^T
+// out_r = c0 base_r + c1 sum_{i in N_j} sum_n w_n omega_ij^n zr_in basisA_j(x_i^n) + ycr (.) mu_j
+// out_e = c0 base_e + c1 (same with ze and basisB) + yce (.) mu_j,
+// mu_j = An_j(U_j Syn(C^j (.) lambda_j)) (transpose of the C-part).  One block per sphere j.
+template <int LM>
+__global__ __launch_bounds__(256) void k_apply_LTZ(int M, int N, int LY, const double* __restrict__ Y,
+                                                    const double* __restrict__ leb, const double* __restrict__ xyz,
+                                                    const double* __restrict__ rad, const int* __restrict__ nptr,
+                                                    const int* __restrict__ nidx, const double* __restrict__ f,
+                                                    const double* __restrict__ U, const double* __restrict__ sgr,
+                                                    const double* __restrict__ ycr, const double* __restrict__ yce,
+                                                    const double* __restrict__ Cl, int LUR, double kappa, double eta,
+                                                    int nterms, const double* __restrict__ base, double c0,
+                                                    const double* __restrict__ zr, const double* __restrict__ ze,
+                                                    double c1, const double* __restrict__ lam, int LLAM,
+                                                    double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double gg[kMaxN];
+  __shared__ double cl[L], mu[L];
+  __shared__ double red[8 * L];
+  const int j = blockIdx.x;
+  if (lam) {
+    for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t];
+    __syncthreads();
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      const double* Yn = Y + (long)n * LY;
+      double a = 0.0;
+#pragma unroll 9
+      for (int t = 0; t < L; ++t) a += Yn[t] * cl[t];
+      gg[n] = U[(long)j * N + n] * a;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+      double a = 0.0;
+      for (int n = 0; n < N; ++n) a += leb[4 * n + 3] * Y[(long)n * LY + t] * gg[n];
+      mu[t] = a;
+    }
+  } else {
+    for (int t = threadIdx.x; t < L; t += blockDim.x) mu[t] = 0.0;
+  }
+  double accA[L], accB[L];
+#pragma unroll
+  for (int t = 0; t < L; ++t) { accA[t] = 0.0; accB[t] = 0.0; }
+  if (zr) {
+    const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
+    double isg[LM + 1];
+#pragma unroll
+    for (int l = 0; l <= LM; ++l) isg[l] = 1.0 / sgr[j * LUR + l];
+    const int q0 = nptr[j], nq = nptr[j + 1] - q0;
+    for (int pidx = threadIdx.x; pidx < nq * N; pidx += blockDim.x) {
+      const int a = pidx / N, n = pidx - a * N;
+      const int i = nidx[q0 + a];
+      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const double t2 = vx * vx + vy * vy + vz * vz;
+      if (t2 >= 1.0) continue;
+      const double fv = f[(long)i * N + n];
+      const double om = (fv > 1.0 ? 1.0 / fv : 1.0) * chi_eta(sqrt(t2), eta);
+      if (om == 0.0) continue;
+      const double wom = leb[4 * n + 3] * om;
+      const double cA = wom * zr[(long)i * N + n], cB = wom * ze[(long)i * N + n];
+      double sg[LM + 1];
+      sigma_weights<LM, double>(kappa * kappa * rj * rj * t2, nterms, sg);
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) sg[l] *= cB * isg[l];
+      for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
+        accA[idx] += cA * S;
+        accB[idx] += sg[l] * S;
+      });
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    double a = wave_sum(accA[t]);
+    double b = wave_sum(accB[t]);
+    if (lane == 0) { red[wid * 2 * L + t] = a; red[wid * 2 * L + L + t] = b; }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < nw; ++w) { a += red[w * 2 * L + t]; b += red[w * 2 * L + L + t]; }
+    const int l = deg_of(t);
+    const long ir = (long)j * L + t, ie = (long)(M + j) * L + t;
+    double orr = c1 * a + ycr[j * LUR + l] * mu[t];
+    double oe = c1 * b + yce[j * LUR + l] * mu[t];
+    if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
+    out[ir] = orr;
+    out[ie] = oe;
+  }
+}
+
+// ---------------------------------------------------------- Krylov helpers
+// part[v * nb + b] = sum over block b's range of V[v][k] * w[k]
+__global__ __launch_bounds__(256) void k_mdot_part(long D, int nv, const double* __restrict__ V, long ldv,
+                                                    const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[16];
+  const int v = blockIdx.y;
+  const long chunk = (D + gridDim.x - 1) / gridDim.x;
+  const long k0 = blockIdx.x * chunk, k1 = min(D, k0 + chunk);
+  double s = 0.0;
+  const double* Vv = V + v * ldv;
+  for (long k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += Vv[k] * w[k];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(long)v * gridDim.x + blockIdx.x] = s;
+}
+__global__ __launch_bounds__(256) void k_mdot_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(long)v * nb + b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[v] = s;
+}
+// w -= sum_v V[v] h[v]
+__global__ void k_mupdate(long D, int nv, const double* __restrict__ V, long ldv, const double* __restrict__ h,
+                          double* __restrict__ w) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= D) return;
+  double s = w[k];
+  for (int v = 0; v < nv; ++v) s -= V[v * ldv + k] * h[v];
+  w[k] = s;
+}
+// y = a x + b y
+__global__ void k_axpby(long D, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k < D) y[k] = a * x[k] + b * y[k];
+}
+// y = sum_v V[v] c[v]
+__global__ void k_mcomb(long D, int nv, const double* __restrict__ V, long ldv, const double* __restrict__ c,
+                        double* __restrict__ y) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= D) return;
+  double s = 0.0;
+  for (int v = 0; v < nv; ++v) s += V[v * ldv + k] * c[v];
+  y[k] = s;
+}
+
+// E = sum_j q_j X_r,j00 / (2 sqrt(4 pi))   (Sec. 3 energy equation, psi_r(x_j) = X_r,j00 Y_00)
+__global__ __launch_bounds__(1024) void k_energy(int M, int L, const double* __restrict__ X, const double* __restrict__ q,
+                                                 double* __restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) s += q[j] * X[(long)j * L];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = s * 0.14104739588693907;  // 1/(2 sqrt(4 pi))
+}
+
+}  // namespace ddlpb

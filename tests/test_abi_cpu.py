@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+symbol declared in include/ddlpb.h, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_00552_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ddlpb.h")).read()
+    return sorted(set(re.findall(r"\b(ddlpb_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_symbols()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def _setup(**kw):
+    args = dict(M=2, x=np.array([[0, 0, 0], [1.0, 0, 0]]), r=np.array([1.5, 1.5]), q=np.array([0.5, -0.5]),
+                e1=1.0, e2=78.54, kap=0.104, lmax=4, nleb=110, p=0)
+    args.update(kw)
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.ddlpb_setup(args["M"], _lib.ptr(np.ascontiguousarray(args["x"], dtype=np.float64)),
+                         _lib.ptr(np.ascontiguousarray(args["r"], dtype=np.float64)),
+                         _lib.ptr(np.ascontiguousarray(args["q"], dtype=np.float64)),
+                         args["e1"], args["e2"], args["kap"], args["lmax"], args["nleb"], args["p"], ctypes.byref(h))
+    if rc == 0:
+        lib.ddlpb_free(h)
+    return rc
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), 0),
+    (dict(r=np.array([1.5, -1.0])), -1),
+    (dict(x=np.array([[0, 0, 0], [np.nan, 0, 0]])), -1),
+    (dict(e2=0.0), -1),
+    (dict(kap=0.0), -1),
+    (dict(lmax=11), -1),
+    (dict(nleb=111), -1),
+    (dict(lmax=9, nleb=110), -1),   # degree 17 < 2 lmax
+    (dict(x=np.array([[0, 0, 0], [0, 0, 0]])), -2),
+    (dict(M=0), -1),
+])
+def test_setup_validation(kw, code):
+    assert _setup(**kw) == code
+
+
+def test_call_order_and_options():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0]])
+    r = np.array([1.5, 1.5])
+    q = np.array([0.5, -0.5])
+    assert lib.ddlpb_setup(2, _lib.ptr(x), _lib.ptr(r), _lib.ptr(q), 1.0, 78.54, 0.104, 4, 110, 0, ctypes.byref(h)) == 0
+    F = np.zeros((2, 3))
+    assert lib.ddlpb_adjoint(h, 1e-8) == -6
+    assert lib.ddlpb_forces(h, _lib.ptr(F)) == -6
+    assert lib.ddlpb_set_option(h, b"eta", 0.2) == 0
+    assert lib.ddlpb_set_option(h, b"eta", 1.5) == -1
+    assert lib.ddlpb_set_option(h, b"nonsense", 1.0) == -1
+    assert lib.ddlpb_workspace_bytes(h) > 0
+    assert lib.ddlpb_strerror(-5) == b"solver did not converge"
+    lib.ddlpb_free(h)
+    lib.ddlpb_free(None)
