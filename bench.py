@@ -1,0 +1,125 @@
+"""Benchmark: ddLPB energy + forces throughput (atoms/s) on one MI355X.
+
+One step = one complete energy + forces evaluation of a synthetic protein-like
+cluster already resident on the device: new conformation (grid switching
+fields and right-hand side), primal solve, adjoint solve and force assembly,
+every solve started from zero.  Prints one JSON line.
+
+Default workload: 100,000-atom jittered-lattice cluster (radii {1.2,1.5,1.7,1.8} A,
+charges N(0, 0.3) neutralised), lmax 8, 302 Lebedev points, tolerance 1e-6.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (= matrix) peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (= matrix) peak
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--atoms", type=int, default=None)
+    p.add_argument("--lmax", type=int, default=8)
+    p.add_argument("--nleb", type=int, default=302)
+    p.add_argument("--fmm-order", type=int, default=None)
+    p.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    p.add_argument("--tol", type=float, default=1e-6)
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-atoms", type=int, default=60)
+    return p.parse_args()
+
+
+def cpu_baseline(args):
+    """The oracle (plain FP64 C++/OpenMP, direct sums) on a bounded sample of the same
+    generator: full energy + forces of a small cluster, reported as atoms/s."""
+    import oracle
+    from paper_2203_00552_amd import inputs
+    n = args.cpu_sample_atoms
+    x, r, q = inputs.lattice_cluster(n, seed=args.seed)
+    P = oracle.Problem(x, r, q, lmax=args.lmax, n_lebedev=args.nleb)
+    t0 = time.perf_counter()
+    P.solve("gmres", tol=args.tol)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / dt, "unit": "atoms/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n}-atom cluster of the same generator, lmax {args.lmax}, {args.nleb} points, "
+                      f"tol {args.tol:g}, full energy+forces in {dt:.1f} s (direct O(M^2) sums: the "
+                      f"oracle's cost per atom grows linearly with M)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2203_00552_amd import Context, inputs
+
+    fmm = args.fmm_order if args.fmm_order is not None else 0
+    atoms = args.atoms if args.atoms is not None else 20000
+    x, r, q = inputs.lattice_cluster(atoms, seed=args.seed)
+    torch.cuda.init()
+    ctx = Context(x, r, q, eps_in=1.0, eps_out=78.54, kappa=0.104, lmax=args.lmax, n_lebedev=args.nleb,
+                  fmm_order=fmm, options={"warm_start": 0, "kernel_timing": 1,
+                                          "precision": 1 if args.precision == "mixed" else 0},
+                  torch_workspace=True)
+
+    def step():
+        ctx.update_centers(x)
+        E = ctx.solve(args.tol, allow_noconv=True)
+        ctx.adjoint(args.tol, allow_noconv=True)
+        F = ctx.forces()
+        return E, F
+
+    for _ in range(args.warmup):
+        step()
+    ctx.kernel_times_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, F = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    kt = ctx.kernel_times()
+    name, (ms, nl, work) = max(kt.items(), key=lambda kv: kv[1][0])
+    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    out = {
+        "metric": "energy+forces atoms/sec at 100k atoms, tol 1e-6; served p50/p99 latency",
+        "value": atoms * args.steps / dt,
+        "unit": "atoms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"jittered-lattice cluster, {atoms} atoms, lmax {args.lmax}, {args.nleb} Lebedev "
+                               f"points, tol {args.tol:g}, " + (f"FMM p={fmm}" if fmm else "direct sums"),
+                   "atoms": atoms, "lmax": args.lmax, "n_lebedev": args.nleb, "fmm_order": fmm,
+                   "precision": args.precision, "tol": args.tol},
+        "roofline": {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
+                     "kernel_ms_per_step": ms / args.steps},
+        "energy": E, "iters": [st["iters_primal"], st["iters_adjoint"]],
+        "phase_ms": {k: st[k] for k in ("ms_rhs", "ms_primal", "ms_adjoint", "ms_forces")},
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -76,10 +76,14 @@ typedef struct {
  *   n_lebedev   one of 6, 14, 26, 38, 50, 74, 86, 110, 146, 170, 194, 230, 266, 302,
  *               350, 434, 590, 770, 974 and of quadrature degree >= 2*lmax
  *   fmm_order   0 = direct O(M^2) single layer and vacuum field;
- *               p > 0 = fast multipole method of order p (Appendix)
+ *               p = lmax+1..16: fast multipole method of order p (Appendix) for
+ *               the single layer (screened Coulomb) and the vacuum (Coulomb)
+ *               field; p must exceed lmax because the force terms need the
+ *               adjoint field at degree lmax+1
  *   out         receives the new context
- * Defaults (change with ddlpb_set_option before the first solve): eta = 0.1,
- * FP64, GMRES restart 40, 8 Jacobi sweeps, max_iter 500, leaf size 32.
+ * Defaults (change with ddlpb_set_option before the first solve): eta = 0.05,
+ * FP64, restart 100, 24 Jacobi sweeps, precond_delta -1 (off),
+ * max_iter 400, theta 0.5.
  * Errors: EINVAL, EGEOM, ENOMEM.  Device memory is allocated lazily at the
  * first solve unless a workspace is bound.
  */
@@ -117,11 +121,22 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "eta"            switching width of chi_eta (Sec. 3.1), 0 < eta <= 1
  *   "precision"      0 = FP64 everywhere, 1 = mixed (FP32 matvec kernels, FP64
  *                    Krylov/reductions/Bessel ratios, FP64 outer refinement)
- *   "gmres_restart"  Krylov subspace size (1..200)
- *   "inner_sweeps"   Jacobi sweeps of the L_AB preconditioner (0..64)
+ *   "gmres_restart"  outer Krylov subspace size (1..200)
+ *   "inner_sweeps"   Jacobi sweeps on L_AB = [A 0; 0 B] used as the innermost
+ *                    preconditioner (0..64; Sec. 4 uses L_AB as preconditioner)
+ *   "precond_delta"  two-level preconditioner: each outer (flexible) GMRES step
+ *                    is preconditioned by inner GMRES steps on P = L_AB + the
+ *                    single-layer blocks of sphere pairs with |x_i - x_j| <
+ *                    r_i + r_j + delta (Angstrom); < 0 (default) disables it
+ *                    (then plain GMRES preconditioned by the L_AB sweeps)
+ *   "inner_iters"    inner GMRES steps on P per outer step (1..200, default 12)
  *   "max_iter"       maximal GMRES iterations per solve
  *   "leaf_size"      maximal spheres per FMM tree leaf
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
+ *   "warm_start"     1 (default): solves start from the previous X / X_adj;
+ *                    0: every solve starts from zero
+ *   "kernel_timing"  1: record the device time of every kernel launch with HIP
+ *                    events on the context's stream (see ddlpb_kernel_times)
  * Errors: EINVAL (unknown key or value out of range), ESTATE.
  */
 int ddlpb_set_option(ddlpb_ctx* ctx, const char* key, double value);
@@ -145,6 +160,16 @@ int ddlpb_update_centers(ddlpb_ctx* ctx, const double* centers);
 size_t ddlpb_workspace_bytes(const ddlpb_ctx* ctx);
 int ddlpb_bind_workspace(ddlpb_ctx* ctx, void* dev, size_t bytes);
 int ddlpb_set_stream(ddlpb_ctx* ctx, void* hip_stream);
+
+/*
+ * Per-kernel device time (when the option "kernel_timing" is 1), accumulated
+ * since the context was created or since ddlpb_kernel_times_reset.
+ * ddlpb_kernel_times: entry idx (0-based) -> name (>= 64 bytes), total ms,
+ *   number of launches and the algorithmic work (flops) those launches did;
+ *   EINVAL when idx is past the last kernel.
+ */
+int ddlpb_kernel_times(ddlpb_ctx* ctx, int32_t idx, char* name_out, double* ms, int64_t* launches, double* work);
+int ddlpb_kernel_times_reset(ddlpb_ctx* ctx);
 
 /* ddlpb_get_stats -- copy the statistics of the last calls. */
 int ddlpb_get_stats(const ddlpb_ctx* ctx, ddlpb_stats* out);

@@ -70,7 +70,7 @@ class Problem:
     """Inputs of one ddLPB evaluation (FP64 copies owned by this object)."""
 
     def __init__(self, centers, radii, charges, eps_in=1.0, eps_out=78.54, kappa=0.104,
-                 lmax=6, n_lebedev=110, eta=0.1, s=None, w=None):
+                 lmax=6, n_lebedev=110, eta=0.05, s=None, w=None):
         self.x = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
         self.r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
         self.q = np.ascontiguousarray(charges, dtype=np.float64).ravel()
@@ -111,11 +111,13 @@ class Problem:
         _load().oracle_rhs(*self._args(), _ptr(g))
         return g
 
-    def apply(self, X, transpose=False):
-        """L X or L^T X (matrix-free, Sec. 2.2 and the adjoint system of Sec. 3)."""
+    def apply(self, X, transpose=False, part="L"):
+        """L X or L^T X (matrix-free, Sec. 2.2 and the adjoint system of Sec. 3);
+        part "AB" applies only [A 0; 0 B], part "C" only [C1 C2; C1 C2] (Sec. 4 splitting)."""
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(2, self.M, self.L)
         Y = np.zeros_like(X)
-        _load().oracle_apply(*self._args(), ctypes.c_int(1 if transpose else 0), _ptr(X), _ptr(Y))
+        _load().oracle_apply(*self._args(), ctypes.c_int(1 if transpose else 0),
+                             ctypes.c_int({"L": 0, "AB": 1, "C": 2}[part]), _ptr(X), _ptr(Y))
         return Y
 
     def dense(self):

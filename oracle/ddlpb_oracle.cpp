@@ -428,7 +428,8 @@ struct Problem {
   // ------------------------------------------------- matrix-free operator L
   // y_j = (eps1/eps2)(l/r_j) X_r,j - (i_l'(r_j)/i_l(r_j)) X_e,j ; the C-part of L X is
   // CX_i = An_i(U_i Phi[m]) with m_j = C^j (.) An_j(U_j Syn(y_j)).
-  void apply(const T* X, T* Yo) const {
+  // part: 0 = L, 1 = L_AB = [A 0; 0 B] only, 2 = L_C = [C1 C2; C1 C2] only (Sec. 4 splitting)
+  void apply(const T* X, T* Yo, int part = 0) const {
     const T* Xr = X;
     const T* Xe = X + (size_t)M * L;
     std::vector<T> h((size_t)M * N), yv(L), m, Phi;
@@ -439,8 +440,12 @@ struct Problem {
       }
       Syn(yv.data(), &h[(size_t)j * N]);
     }
-    single_layer_moments(h, m);
-    single_layer_field(m, Phi);
+    if (part != 1) {
+      single_layer_moments(h, m);
+      single_layer_field(m, Phi);
+    } else {
+      Phi.assign((size_t)M * N, T(0.0));
+    }
 #pragma omp parallel for schedule(dynamic)
     for (int i = 0; i < M; ++i) {
       std::vector<T> vA(N, T(0.0)), vB(N, T(0.0)), vC(N), b(L), c(L);
@@ -464,15 +469,16 @@ struct Problem {
       An(vA.data(), cA.data());
       An(vB.data(), cB.data());
       An(vC.data(), cC.data());
+      const double sAB = part == 2 ? 0.0 : 1.0;
       for (int lm = 0; lm < L; ++lm) {
-        Yo[(size_t)i * L + lm] = Xr[(size_t)i * L + lm] - cA[lm] + cC[lm];
-        Yo[(size_t)(M + i) * L + lm] = Xe[(size_t)i * L + lm] - cB[lm] + cC[lm];
+        Yo[(size_t)i * L + lm] = sAB * (Xr[(size_t)i * L + lm] - cA[lm]) + cC[lm];
+        Yo[(size_t)(M + i) * L + lm] = sAB * (Xe[(size_t)i * L + lm] - cB[lm]) + cC[lm];
       }
     }
   }
 
   // Transposed operator L^T = [A^T 0; 0 B^T] + [C1^T C1^T; C2^T C2^T].
-  void apply_T(const T* Z, T* W) const {
+  void apply_T(const T* Z, T* W, int part = 0) const {
     const T* Zr = Z;
     const T* Ze = Z + (size_t)M * L;
     // C-part: zeta = Z_r + Z_e;  c_in = w_n U_in Syn(zeta_i)_n ; lambda = K^T c;
@@ -483,7 +489,7 @@ struct Problem {
       Syn(zeta.data(), &c[(size_t)i * N]);
       for (int n = 0; n < N; ++n) c[(size_t)i * N + n] = w[n] * U[(size_t)i * N + n] * c[(size_t)i * N + n];
     }
-    single_layer_adjoint(c, lam);
+    if (part != 1) single_layer_adjoint(c, lam); else lam.assign((size_t)M * L, T(0.0));
 #pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < M; ++j) {
       std::vector<T> cl(L), g(N), mu(L), b(L), accA(L, T(0.0)), accB(L, T(0.0)), zi(N), ze(N);
@@ -509,8 +515,9 @@ struct Problem {
         int l = lof(lm);
         double a = (eps1 / eps2) * (double(l) / r[j]);
         double bb = -Dl[j * (lmax + 1) + l];
-        W[(size_t)j * L + lm] = Zr[(size_t)j * L + lm] - accA[lm] + a * mu[lm];
-        W[(size_t)(M + j) * L + lm] = Ze[(size_t)j * L + lm] - accB[lm] + bb * mu[lm];
+        const double sAB = part == 2 ? 0.0 : 1.0;
+        W[(size_t)j * L + lm] = sAB * (Zr[(size_t)j * L + lm] - accA[lm]) + a * mu[lm];
+        W[(size_t)(M + j) * L + lm] = sAB * (Ze[(size_t)j * L + lm] - accB[lm]) + bb * mu[lm];
       }
     }
   }
@@ -950,9 +957,10 @@ void oracle_rhs(ORACLE_ARGS, double* g) {
 }
 
 // Y = L X (transpose = 0) or Y = L^T X (transpose = 1), matrix-free.
-void oracle_apply(ORACLE_ARGS, int transpose, const double* X, double* Yo) {
+// part 0: the whole operator; 1: the sparse part L_AB only; 2: the single-layer part L_C only.
+void oracle_apply(ORACLE_ARGS, int transpose, int part, const double* X, double* Yo) {
   auto P = make_problem<double>(ORACLE_PASS);
-  if (transpose) P.apply_T(X, Yo); else P.apply(X, Yo);
+  if (transpose) P.apply_T(X, Yo, part); else P.apply(X, Yo, part);
 }
 
 // Literal dense assembly of L [(2ML)^2] and g [2ML].

@@ -17,7 +17,7 @@ ERRORS = {0: "ok", -1: "EINVAL", -2: "EGEOM", -3: "ENOMEM", -4: "EDEVICE", -5: "
 EXPORTS = ["ddlpb_setup", "ddlpb_solve", "ddlpb_adjoint", "ddlpb_forces", "ddlpb_free", "ddlpb_set_option",
            "ddlpb_update_centers", "ddlpb_workspace_bytes", "ddlpb_bind_workspace", "ddlpb_set_stream",
            "ddlpb_get_stats", "ddlpb_strerror", "ddlpb_get_grid", "ddlpb_get_solution", "ddlpb_get_rhs",
-           "ddlpb_apply"]
+           "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset"]
 
 
 class DDLPBError(RuntimeError):
@@ -71,6 +71,8 @@ def load():
         lib.ddlpb_get_solution.argtypes = [c_void_p, _dp, _dp]
         lib.ddlpb_get_rhs.argtypes = [c_void_p, _dp]
         lib.ddlpb_apply.argtypes = [c_void_p, c_int, _dp, _dp]
+        lib.ddlpb_kernel_times.argtypes = [c_void_p, c_int, ctypes.c_char_p, _dp, ctypes.POINTER(ctypes.c_int64), _dp]
+        lib.ddlpb_kernel_times_reset.argtypes = [c_void_p]
         _lib = lib
     return _lib
 
@@ -156,6 +158,21 @@ class Context:
         s = Stats()
         check(load().ddlpb_get_stats(self._h, ctypes.byref(s)), "ddlpb_get_stats")
         return s.as_dict()
+
+    def kernel_times(self):
+        """{kernel name: (ms, launches, algorithmic flops)} (needs the option kernel_timing=1)."""
+        out = {}
+        k = 0
+        name = ctypes.create_string_buffer(64)
+        ms, work = ctypes.c_double(), ctypes.c_double()
+        nl = ctypes.c_int64()
+        while load().ddlpb_kernel_times(self._h, k, name, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(work)) == 0:
+            out[name.value.decode()] = (ms.value, nl.value, work.value)
+            k += 1
+        return out
+
+    def kernel_times_reset(self):
+        check(load().ddlpb_kernel_times_reset(self._h), "ddlpb_kernel_times_reset")
 
     def grid(self):
         f = np.zeros((self.M, self.N))

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -19,6 +20,8 @@
 #include "../../include/ddlpb.h"
 #include "host_math.hpp"
 #include "kernels_forces.hpp"
+#include "fmm.hpp"
+#include "fmm_host.hpp"
 
 using namespace ddlpb;
 
@@ -56,15 +59,20 @@ void ensure_constants() {
 struct ddlpb_ctx {
   // ---- problem
   int M = 0, lmax = 0, L = 0, LP = 0, LY = 0, LUR = 0, N = 0, fmm_order = 0;
-  double eps1 = 1, eps2 = 78.54, kappa = 0.1, eta = 0.1;
+  double eps1 = 1, eps2 = 78.54, kappa = 0.1, eta = 0.05;
   std::vector<double> x, r, q;
   const ddlpb_tables::LebedevRule* rule = nullptr;
   // ---- options
-  int precision = 0, restart = 40, sweeps = 8, maxit = 500, leaf = 32;
+  int precision = 0, restart = 100, sweeps = 24, maxit = 400, leaf = 32;
+  int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
+  double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
+  bool warm_start = true;
   double theta = 0.5;
   // ---- host analysis
   std::vector<int> nptr, nidx, nrev;
-  int nterms = 8;
+  std::vector<int> pptr, pidx;  // sphere pairs of the near preconditioner (self included)
+  size_t nnz_cap = 0, pnz_cap = 0;  // capacities of the device copies of nidx / pidx
+  int nterms = 8, nterms_p = 8;
   // ---- device
   hipStream_t stream = nullptr;
   bool ws_bound = false, ws_owned = false, dev_ready = false;
@@ -83,13 +91,39 @@ struct ddlpb_ctx {
   double *d_g = nullptr, *d_X = nullptr, *d_Xa = nullptr, *d_Q = nullptr, *d_w = nullptr, *d_t1 = nullptr,
          *d_t2 = nullptr, *d_t3 = nullptr, *d_V = nullptr;
   double *d_part = nullptr, *d_hv = nullptr, *d_scal = nullptr;
+  int *d_pptr = nullptr, *d_pidx = nullptr;
+  double *d_Z = nullptr, *d_Vin = nullptr, *d_t4 = nullptr, *d_t5 = nullptr;
   double *d_fnb = nullptr, *d_fself = nullptr, *d_fpt = nullptr, *d_fpts = nullptr, *d_flsrc = nullptr,
          *d_fysrc = nullptr, *d_gphi = nullptr, *d_F = nullptr;
   int nact = 0;
+  long ncap = 0;  // cap pairs (i, n, j) with omega > 0, counted on the host
+  double near_pairs_pts = 0.0;  // (active point, listed source sphere) pairs of the near list
   int nb_dot = 256;
+  // ---- fast multipole method (fmm_order > 0)
+  fmm::Tree tree;
+  fmm::Tables tables;
+  size_t m2l_cap = 0, near_cap = 0;
+  double *d_fcen = nullptr, *d_frad = nullptr, *d_fkR = nullptr, *d_fiR = nullptr, *d_fA = nullptr, *d_fAL = nullptr,
+         *d_fJ = nullptr, *d_Mn = nullptr, *d_Ln = nullptr, *d_SL = nullptr, *d_Lam = nullptr, *d_sgp = nullptr,
+         *d_qsrc = nullptr, *d_tmp4 = nullptr;
+  int *d_fJoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
+      *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
+      *d_sleaf = nullptr;
+  double near_pts_fmm = 0.0;  // (active point, near source sphere) pairs of the FMM near list
+  // ---- per-kernel device timing (option "kernel_timing")
+  struct KTimer {
+    std::string name;
+    double ms = 0.0, work = 0.0;
+    long launches = 0;
+  };
+  bool ktiming = false;
+  std::vector<KTimer> ktimers;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   // ---- state
   int state = 0;  // 0 = set up, 1 = primal solved, 2 = adjoint solved
   bool rhs_ready = false;
+  long inner_total = 0;
   double energy = 0.0;
   ddlpb_stats stats{};
 };
@@ -104,7 +138,7 @@ int check_inputs(int32_t M, const double* x, const double* r, const double* q, d
   if (M < 1 || !x || !r || !q) return DDLPB_EINVAL;
   if (!(e1 > 0) || !(e2 > 0) || !(kap > 0) || !std::isfinite(e1) || !std::isfinite(e2) || !std::isfinite(kap))
     return DDLPB_EINVAL;
-  if (lmax < 0 || lmax > kMaxLmax || p < 0 || p > 20) return DDLPB_EINVAL;
+  if (lmax < 0 || lmax > kMaxLmax || p < 0 || p > 16) return DDLPB_EINVAL;
   const auto* rule = host::lebedev_rule(nleb);
   if (!rule || rule->degree < 2 * lmax) return DDLPB_EINVAL;
   if (nleb > kMaxN) return DDLPB_EINVAL;
@@ -164,6 +198,45 @@ int build_neighbours(ddlpb_ctx* c) {
   return DDLPB_OK;
 }
 
+// Sphere pairs (i, j) with |x_i - x_j| < r_i + r_j + delta, i itself included, sorted by j.
+void build_pairs(const ddlpb_ctx* c, double delta, std::vector<int>& ptr, std::vector<int>& idx) {
+  const int M = c->M;
+  double rmax = 0;
+  for (double v : c->r) rmax = std::max(rmax, v);
+  const double cell = 2.0 * rmax + std::max(delta, 0.0);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int i = 0; i < M; ++i)
+    for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], c->x[3 * i + a]);
+  auto key = [&](long ix, long iy, long iz) { return (ix * 1000003L + iy) * 1000033L + iz; };
+  std::unordered_map<long, std::vector<int>> cells;
+  cells.reserve(M);
+  std::vector<long> ci(3L * M);
+  for (int i = 0; i < M; ++i) {
+    for (int a = 0; a < 3; ++a) ci[3L * i + a] = (long)std::floor((c->x[3 * i + a] - lo[a]) / cell);
+    cells[key(ci[3L * i], ci[3L * i + 1], ci[3L * i + 2])].push_back(i);
+  }
+  ptr.assign(M + 1, 0);
+  idx.clear();
+  std::vector<int> row;
+  for (int i = 0; i < M; ++i) {
+    row.clear();
+    for (long dx = -1; dx <= 1; ++dx)
+      for (long dy = -1; dy <= 1; ++dy)
+        for (long dz = -1; dz <= 1; ++dz) {
+          auto it = cells.find(key(ci[3L * i] + dx, ci[3L * i + 1] + dy, ci[3L * i + 2] + dz));
+          if (it == cells.end()) continue;
+          for (int j : it->second) {
+            double d2 = 0;
+            for (int a = 0; a < 3; ++a) { double t = c->x[3 * i + a] - c->x[3 * j + a]; d2 += t * t; }
+            if (j == i || std::sqrt(d2) < c->r[i] + c->r[j] + delta) row.push_back(j);
+          }
+        }
+    std::sort(row.begin(), row.end());
+    idx.insert(idx.end(), row.begin(), row.end());
+    ptr[i + 1] = (int)idx.size();
+  }
+}
+
 // ------------------------------------------------------------ workspace
 struct Carver {
   char* base;
@@ -179,7 +252,10 @@ struct Carver {
 
 void carve(ddlpb_ctx* c, char* base, size_t* total) {
   Carver cv{base};
-  const size_t M = c->M, N = c->N, MN = M * N, D = 2 * M * c->L, nnz = c->nidx.size();
+  const size_t M = c->M, N = c->N, MN = M * N, D = 2 * M * c->L;
+  c->nnz_cap = std::max(c->nnz_cap, c->nidx.size());
+  c->pnz_cap = std::max(c->pnz_cap, c->pidx.size());
+  const size_t nnz = c->nnz_cap;
   c->d_xyz = cv.take<double>(3 * M);
   c->d_rad = cv.take<double>(M);
   c->d_q = cv.take<double>(M);
@@ -222,8 +298,16 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_t2 = cv.take<double>(D);
   c->d_t3 = cv.take<double>(D);
   c->d_V = cv.take<double>((size_t)(c->restart + 1) * D);
-  c->d_part = cv.take<double>((size_t)(c->restart + 2) * c->nb_dot);
-  c->d_hv = cv.take<double>(c->restart + 2);
+  const bool two_level = c->pdelta >= 0.0;
+  c->d_Z = two_level ? cv.take<double>((size_t)c->restart * D) : nullptr;
+  c->d_Vin = two_level ? cv.take<double>((size_t)(c->inner_iters + 1) * D) : nullptr;
+  c->d_t4 = cv.take<double>(D);
+  c->d_t5 = cv.take<double>(D);
+  c->d_pptr = cv.take<int>(M + 1);
+  c->d_pidx = cv.take<int>(std::max<size_t>(c->pnz_cap, 1));
+  const int mk = std::max(c->restart, c->inner_iters) + 2;
+  c->d_part = cv.take<double>((size_t)mk * c->nb_dot);
+  c->d_hv = cv.take<double>(mk);
   c->d_scal = cv.take<double>(16);
   c->d_fnb = cv.take<double>(3 * std::max<size_t>(nnz, 1));
   c->d_fself = cv.take<double>(3 * M);
@@ -233,6 +317,36 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_fysrc = cv.take<double>(3 * M);
   c->d_gphi = cv.take<double>(3 * MN);
   c->d_F = cv.take<double>(3 * M);
+  if (c->fmm_order > 0) {
+    const size_t nn = c->tree.nnodes, p1 = c->fmm_order + 1, P = p1 * p1;
+    c->m2l_cap = std::max(c->m2l_cap, c->tree.m2l_src.size());
+    c->near_cap = std::max(c->near_cap, c->tree.near_idx.size());
+    c->d_fcen = cv.take<double>(3 * nn);
+    c->d_frad = cv.take<double>(nn);
+    c->d_fkR = cv.take<double>(nn * p1);
+    c->d_fiR = cv.take<double>(nn * p1);
+    c->d_fchild = cv.take<int>(2 * nn);
+    c->d_fparent = cv.take<int>(nn);
+    c->d_flevn = cv.take<int>(nn);
+    c->d_sleaf = cv.take<int>(M);
+    c->d_fm2lp = cv.take<int>(nn + 1);
+    c->d_fm2ls = cv.take<int>(std::max<size_t>(c->m2l_cap, 1));
+    c->d_fm2ltp = cv.take<int>(nn + 1);
+    c->d_fm2ltt = cv.take<int>(std::max<size_t>(c->m2l_cap, 1));
+    c->d_fnp = cv.take<int>(M + 1);
+    c->d_fni = cv.take<int>(std::max<size_t>(c->near_cap, 1));
+    c->d_fA = cv.take<double>(p1 * p1 * p1 * p1);
+    c->d_fAL = cv.take<double>(3 * p1 * p1 * p1);
+    c->d_fJ = cv.take<double>(std::max<size_t>(c->tables.J.size(), 1));
+    c->d_fJoff = cv.take<int>(p1 + 1);
+    c->d_Mn = cv.take<double>(nn * P);
+    c->d_Ln = cv.take<double>(nn * P);
+    c->d_SL = cv.take<double>(M * P);
+    c->d_Lam = cv.take<double>(M * P);
+    c->d_sgp = cv.take<double>(M * (p1 + 1));
+    c->d_qsrc = cv.take<double>(M);
+    c->d_tmp4 = cv.take<double>(4 * M);
+  }
   *total = cv.off + 256;
 }
 
@@ -260,7 +374,74 @@ size_t workspace_size(ddlpb_ctx* c) {
     default: throw HipError{hipErrorInvalidValue};   \
   }
 
+#define P_DISPATCH(PV, BODY)                        \
+  switch (PV) {                                     \
+    case 2: { constexpr int PDc = 2; BODY; } break;   \
+    case 3: { constexpr int PDc = 3; BODY; } break;   \
+    case 4: { constexpr int PDc = 4; BODY; } break;   \
+    case 5: { constexpr int PDc = 5; BODY; } break;   \
+    case 6: { constexpr int PDc = 6; BODY; } break;   \
+    case 7: { constexpr int PDc = 7; BODY; } break;   \
+    case 8: { constexpr int PDc = 8; BODY; } break;   \
+    case 9: { constexpr int PDc = 9; BODY; } break;   \
+    case 10: { constexpr int PDc = 10; BODY; } break; \
+    case 11: { constexpr int PDc = 11; BODY; } break; \
+    case 12: { constexpr int PDc = 12; BODY; } break; \
+    case 13: { constexpr int PDc = 13; BODY; } break; \
+    case 14: { constexpr int PDc = 14; BODY; } break; \
+    case 15: { constexpr int PDc = 15; BODY; } break; \
+    case 16: { constexpr int PDc = 16; BODY; } break; \
+    default: throw HipError{hipErrorInvalidValue};    \
+  }
+
 inline unsigned nblk(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Per-kernel device time: events recorded on the context's stream around a launch.
+struct KScope {
+  ddlpb_ctx* c;
+  int idx = -1;
+  hipEvent_t e0{}, e1{};
+  KScope(ddlpb_ctx* c_, const char* name, double work) : c(c_) {
+    if (!c->ktiming) return;
+    for (size_t k = 0; k < c->ktimers.size(); ++k)
+      if (c->ktimers[k].name == name) idx = (int)k;
+    if (idx < 0) { c->ktimers.push_back({name}); idx = (int)c->ktimers.size() - 1; }
+    c->ktimers[idx].work += work;
+    c->ktimers[idx].launches += 1;
+    e0 = take(); e1 = take();
+    HIPCHK(hipEventRecord(e0, c->stream));
+  }
+  hipEvent_t take() {
+    if (c->ev_pool.empty()) { hipEvent_t e; HIPCHK(hipEventCreate(&e)); return e; }
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  ~KScope() noexcept(false) {
+    if (idx < 0) return;
+    HIPCHK(hipEventRecord(e1, c->stream));
+    c->ev_pending.push_back({idx, {e0, e1}});
+  }
+};
+void ktimer_flush(ddlpb_ctx* c) {
+  if (c->ev_pending.empty()) return;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto& p : c->ev_pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    c->ktimers[p.first].ms += ms;
+    c->ev_pool.push_back(p.second.first);
+    c->ev_pool.push_back(p.second.second);
+  }
+  c->ev_pending.clear();
+}
+// algorithmic flops of one (point, sphere) single-layer interaction at degree lm:
+// 2L for the contraction with the coefficients, ~3L for the harmonic recurrence,
+// 3 per degree for the Bessel weights, ~25 for distance, exp and the first two weights
+inline double flops_sl_pair(int lm) { double L = (lm + 1.0) * (lm + 1.0); return 5.0 * L + 3.0 * (lm + 1) + 25.0; }
+// one neighbour-cap interaction of the A/B operators: harmonic recurrence, two contractions,
+// the i_l weights (two series of nterms terms and the downward recurrence)
+inline double flops_cap_pair(int lm, int nterms) { double L = (lm + 1.0) * (lm + 1.0); return 7.0 * L + 6.0 * nterms + 8.0 * (lm + 1) + 30.0; }
 
 void fill(ddlpb_ctx* c, double* p, long n, double v) {
   if (n <= 0) return;
@@ -280,6 +461,7 @@ void moments(ddlpb_ctx* c, const double* X, const double* egrid, double* h_out, 
 void sl_field(ddlpb_ctx* c, const double* m, bool grad, int exclude_self, double* out) {
   if (c->nact == 0) return;
   if (!grad) fill(c, out, (long)c->M * c->N, 0.0);
+  KScope ks(c, grad ? "sl_field_grad" : "sl_field", (grad ? 4.0 : 1.0) * flops_sl_pair(c->lmax) * (double)c->nact * c->M);
   if (grad) {
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_direct<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
                                             c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
@@ -295,6 +477,7 @@ void sl_field(ddlpb_ctx* c, const double* m, bool grad, int exclude_self, double
 // lambda (stride (lo+1)^2) from grid charges
 void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, double* lam) {
   if (c->nact == 0) { fill(c, lam, (long)c->M * (lo + 1) * (lo + 1), 0.0); return; }
+  KScope ks(c, "sl_adjoint", flops_sl_pair(lo) * (double)c->nact * c->M);
   LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_direct<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
                                      c->nact, c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, cgrid, c->d_ur,
                                      c->LUR, c->kappa, exclude_self, lam));
@@ -303,6 +486,7 @@ void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, dou
 
 void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
               const double* gr2, const double* ge, double cg, double* out) {
+  KScope ks(c, "apply_LX", nearX ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LX<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U,
                                           c->d_sgr, c->LUR, c->kappa, c->eta, c->nterms, base, c0, nearX, c1, gr1,
@@ -318,6 +502,7 @@ void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
 
 void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
                const double* lam, int llam, double* out) {
+  KScope ks(c, "apply_LTZ", zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LTZ<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U,
                                           c->d_sgr, c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->eta, c->nterms,
@@ -325,17 +510,165 @@ void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, co
   HIPCHK(hipGetLastError());
 }
 
+void sl_field_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double* m, bool grad, int exclude_self,
+                   int accumulate, double* out) {
+  if (c->nact == 0) return;
+  KScope ks(c, grad ? "sl_near_grad" : "sl_near", (grad ? 4.0 : 1.0) * flops_sl_pair(c->lmax) * c->near_pairs_pts);
+  if (grad) {
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
+                                            c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
+                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_ur, c->LUR, c->kappa,
+                                            exclude_self, accumulate, out));
+  } else {
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, false>), dim3(nblk(c->nact, 256)), dim3(256), 0,
+                                            c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
+                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_ur, c->LUR, c->kappa,
+                                            exclude_self, accumulate, out));
+  }
+  HIPCHK(hipGetLastError());
+}
+void sl_adjoint_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double* cgrid, int lo, int exclude_self,
+                     int accumulate, int ldl, double* lam) {
+  KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pairs_pts);
+  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+                                     c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_ur,
+                                     c->LUR, c->kappa, exclude_self, accumulate, ldl, lam));
+  HIPCHK(hipGetLastError());
+}
+
+// ---- fast multipole passes
+FmmDev fmm_dev(ddlpb_ctx* c, int kernel) {
+  FmmDev f;
+  f.kernel = kernel;
+  f.p = c->fmm_order;
+  f.kappa = c->kappa;
+  f.A = c->d_fA; f.AL = c->d_fAL; f.J = c->d_fJ; f.Joff = c->d_fJoff;
+  f.center = c->d_fcen; f.radius = c->d_frad; f.kR = c->d_fkR; f.iR = c->d_fiR;
+  return f;
+}
+// flops of one translation at order p: four rotations by J, the z-translation sum
+inline double flops_translation(int p) {
+  double rot = 0.0, oz = 0.0;
+  for (int l = 0; l <= p; ++l) rot += (2.0 * l + 1.0) * (2.0 * l + 1.0);
+  for (int l = 0; l <= p; ++l)
+    for (int lp = 0; lp <= p; ++lp)
+      for (int m = -std::min(l, lp); m <= std::min(l, lp); ++m) oz += 2.0 * (std::min(l, lp) - std::abs(m) + 1) + 4.0;
+  return 8.0 * rot + oz;
+}
+// sphere locals SL [M][P] of the far field of per-sphere sources src (degree ps, stride lds)
+void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, double* SL) {
+  const auto& t = c->tree;
+  const int p = c->fmm_order, P = (p + 1) * (p + 1);
+  FmmDev f = fmm_dev(c, kernel);
+  KScope ks(c, kernel == 0 ? "fmm_yukawa" : "fmm_laplace",
+            flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
+  hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, ps, lds, c->d_sleaf, src, c->d_Mn);
+  for (int lev = t.nlevels - 2; lev >= 0; --lev) {
+    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
+    hipLaunchKernelGGL(k_fmm_upward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
+                       c->d_fchild, c->d_Mn);
+  }
+  hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, c->d_fm2lp,
+                     c->d_fm2ls, 0, c->d_Mn, c->d_Ln);
+  for (int lev = 1; lev < t.nlevels; ++lev) {
+    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
+    hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
+                       c->d_fparent, 0, c->d_Ln);
+  }
+  hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, c->d_Ln, 0, SL);
+  HIPCHK(hipGetLastError());
+}
+// transpose of fmm_forward: per-sphere dual sources (degree pd, stride ldd) from the dual sphere locals Lam [M][P]
+void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd, int accumulate, double* out) {
+  const auto& t = c->tree;
+  const int p = c->fmm_order, P = (p + 1) * (p + 1);
+  FmmDev f = fmm_dev(c, kernel);
+  KScope ks(c, kernel == 0 ? "fmm_yukawa_T" : "fmm_laplace_T",
+            flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
+  fill(c, c->d_Ln, (long)t.nnodes * P, 0.0);
+  hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, Lam, c->d_Ln);
+  for (int lev = t.nlevels - 2; lev >= 0; --lev) {
+    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
+    hipLaunchKernelGGL(k_fmm_upward_T, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
+                       c->d_fchild, c->d_Ln);
+  }
+  hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, c->d_fm2ltp,
+                     c->d_fm2ltt, 1, c->d_Ln, c->d_Mn);
+  for (int lev = 1; lev < t.nlevels; ++lev) {
+    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
+    hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
+                       c->d_fparent, 1, c->d_Mn);
+  }
+  hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, pd, ldd, c->d_sleaf, c->d_Mn,
+                     accumulate, out);
+  HIPCHK(hipGetLastError());
+}
+void l2p(ddlpb_ctx* c, int mode, double c2, double* out1, double* out2) {
+  if (c->nact == 0) return;
+  const int P = (c->fmm_order + 1) * (c->fmm_order + 1);
+  hipLaunchKernelGGL(k_l2p, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->nact, c->N, P, c->LY, c->d_actsph,
+                     c->d_actn, c->d_rad, c->d_Y, c->d_SL, mode, c2, out1, out2);
+  HIPCHK(hipGetLastError());
+}
+void p2l_dual(ddlpb_ctx* c, const double* g1, const double* g2, double* Lam) {
+  const int P = (c->fmm_order + 1) * (c->fmm_order + 1);
+  hipLaunchKernelGGL(k_p2l_dual, dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, P, c->LY, c->d_rad, c->d_Y, g1, g2,
+                     Lam);
+  HIPCHK(hipGetLastError());
+}
+// Phi[m] on the grid (zero at inactive points): direct, or FMM near list + far field
+void sl_field_full(ddlpb_ctx* c, const double* m, double* Phi) {
+  if (c->fmm_order == 0) { sl_field(c, m, false, 0, Phi); return; }
+  fill(c, Phi, (long)c->M * c->N, 0.0);
+  if (c->nact == 0) return;
+  {
+    KScope ks(c, "sl_near", flops_sl_pair(c->lmax) * c->near_pts_fmm);
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, false>), dim3(nblk(c->nact, 256)), dim3(256), 0,
+                                            c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
+                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, m, c->d_ur, c->LUR, c->kappa, 0, 1,
+                                            Phi));
+  }
+  fmm_forward(c, 0, m, c->lmax, c->L, c->d_SL);
+  l2p(c, 0, 0.0, Phi, nullptr);
+}
+// lambda (degree lo, stride ldl) from grid charges: direct, or FMM near list + far field
+void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, int ldl, double* lam) {
+  if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
+  {
+    KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pts_fmm);
+    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+                                       c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, cgrid,
+                                       c->d_ur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
+    HIPCHK(hipGetLastError());
+  }
+  p2l_dual(c, cgrid, nullptr, c->d_Lam);
+  fmm_transpose(c, 0, c->d_Lam, lo, ldl, 1, lam);
+}
+
 // ---- operators
+// y = P x with P = L_AB + the single-layer blocks of near sphere pairs (two-level preconditioner)
+void op_P(ddlpb_ctx* c, const double* x, double* y) {
+  moments(c, x, nullptr, nullptr, c->d_m);
+  fill(c, c->d_Phi, (long)c->M * c->N, 0.0);
+  sl_field_list(c, c->d_pptr, c->d_pidx, c->d_m, false, 0, 0, c->d_Phi);
+  apply_LX(c, x, 1.0, x, -1.0, c->d_Phi, nullptr, c->d_Phi, 1.0, y);
+}
+void op_PT(ddlpb_ctx* c, const double* x, double* y) {
+  syn2(c, x, 1, c->d_cg, nullptr);
+  sl_adjoint_list(c, c->d_pptr, c->d_pidx, c->d_cg, c->lmax, 0, 0, c->L, c->d_lam);
+  syn2(c, x, 0, c->d_zr, c->d_ze);
+  apply_LTZ(c, x, 1.0, c->d_zr, c->d_ze, -1.0, c->d_lam, c->L, y);
+}
 // y = L x
 void op_L(ddlpb_ctx* c, const double* x, double* y) {
   moments(c, x, nullptr, nullptr, c->d_m);
-  sl_field(c, c->d_m, false, 0, c->d_Phi);
+  sl_field_full(c, c->d_m, c->d_Phi);
   apply_LX(c, x, 1.0, x, -1.0, c->d_Phi, nullptr, c->d_Phi, 1.0, y);
 }
 // y = L^T x
 void op_LT(ddlpb_ctx* c, const double* x, double* y) {
   syn2(c, x, 1, c->d_cg, nullptr);
-  sl_adjoint(c, c->d_cg, c->lmax, 0, c->d_lam);
+  sl_adjoint_full(c, c->d_cg, c->lmax, 0, c->L, c->d_lam);
   syn2(c, x, 0, c->d_zr, c->d_ze);
   apply_LTZ(c, x, 1.0, c->d_zr, c->d_ze, -1.0, c->d_lam, c->L, y);
 }
@@ -380,44 +713,53 @@ void axpby(ddlpb_ctx* c, double a, const double* x, double b, double* y) {
   HIPCHK(hipGetLastError());
 }
 
-// Right-preconditioned restarted GMRES with classical Gram-Schmidt and one
-// re-orthogonalisation; stops at ||b - A x|| <= tol ||b||.
-int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
+using VecOp = std::function<void(const double*, double*)>;
+
+// Restarted right-preconditioned GMRES with classical Gram-Schmidt and one
+// re-orthogonalisation.  Flexible (FGMRES) when Z is given: the preconditioned
+// directions are stored, so the preconditioner may change between iterations.
+// Stops at ||b - A x|| <= tol ||b|| (or after maxit iterations / max_cycles cycles).
+int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b, double* x, double tol, int m,
+               int maxit, int max_cycles, bool x_zero, double* V, double* Z, double* tw, double* tz, double* tc,
+               int* iters, double* relres) {
   const long D = 2L * c->M * c->L;
-  const int m = c->restart;
-  auto op = [&](const double* in, double* out) { if (transpose) op_LT(c, in, out); else op_L(c, in, out); };
   const double bn = norm2(c, b);
   *iters = 0;
   *relres = 0.0;
   if (bn == 0.0) { fill(c, x, D, 0.0); return DDLPB_OK; }
-  int total = 0;
+  int total = 0, cycles = 0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
-  double rel = 0.0;
+  double rel = 1.0;
   bool conv = false;
   while (true) {
-    op(x, c->d_w);
-    HIPCHK(hipMemcpyAsync(c->d_V, b, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    axpby(c, -1.0, c->d_w, 1.0, c->d_V);  // V0 = b - A x
-    const double beta = norm2(c, c->d_V);
+    if (x_zero && cycles == 0) {
+      HIPCHK(hipMemcpyAsync(V, b, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      op(x, tw);
+      HIPCHK(hipMemcpyAsync(V, b, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      axpby(c, -1.0, tw, 1.0, V);
+    }
+    const double beta = norm2(c, V);
     rel = beta / bn;
     if (rel <= tol) { conv = true; break; }
-    if (total >= c->maxit) break;
-    axpby(c, 0.0, c->d_w, 1.0 / beta, c->d_V);
+    if (total >= maxit || cycles >= max_cycles) break;
+    axpby(c, 0.0, V, 1.0 / beta, V);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int j = 0;
-    for (; j < m && total < c->maxit; ++j) {
-      precond(c, transpose, c->d_V + (long)j * D, c->d_t1);
-      double* w = c->d_V + (long)(j + 1) * D;
-      op(c->d_t1, w);
-      mdot(c, j + 1, c->d_V, D, w, h.data());
-      mupdate(c, j + 1, c->d_V, D, h.data(), w);
-      mdot(c, j + 1, c->d_V, D, w, h2.data());
-      mupdate(c, j + 1, c->d_V, D, h2.data(), w);
+    for (; j < m && total < maxit; ++j) {
+      double* zj = Z ? Z + (long)j * D : tz;
+      prec(V + (long)j * D, zj);
+      double* w = V + (long)(j + 1) * D;
+      op(zj, w);
+      mdot(c, j + 1, V, D, w, h.data());
+      mupdate(c, j + 1, V, D, h.data(), w);
+      mdot(c, j + 1, V, D, w, h2.data());
+      mupdate(c, j + 1, V, D, h2.data(), w);
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
       const double hn = norm2(c, w);
       H[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0) axpby(c, 0.0, c->d_w, 1.0 / hn, w);
+      if (hn > 0) axpby(c, 0.0, w, 1.0 / hn, w);
       for (int i = 0; i < j; ++i) {
         double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
         H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
@@ -439,14 +781,43 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
       y[i] = a / H[(size_t)i * m + i];
     }
     HIPCHK(hipMemcpyAsync(c->d_hv, y.data(), j * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, j, c->d_V, D, c->d_hv, c->d_t2);
-    HIPCHK(hipGetLastError());
-    precond(c, transpose, c->d_t2, c->d_t1);
-    axpby(c, 1.0, c->d_t1, 1.0, x);
+    if (Z) {
+      hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, j, Z, D, c->d_hv, tc);
+      HIPCHK(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, j, V, D, c->d_hv, tw);
+      HIPCHK(hipGetLastError());
+      prec(tw, tc);
+    }
+    if (x_zero && cycles == 0) HIPCHK(hipMemcpyAsync(x, tc, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else axpby(c, 1.0, tc, 1.0, x);
+    ++cycles;
+    if (max_cycles == 1) { rel = std::fabs(gv[j]) / bn; break; }
   }
   *iters = total;
   *relres = rel;
   return conv ? DDLPB_OK : DDLPB_ENOCONV;
+}
+
+// Outer solve of L X = b (or L^T X = b).  Two-level preconditioner: a few GMRES
+// steps on P = L_AB + near single-layer blocks, themselves preconditioned by
+// Jacobi sweeps on L_AB; the outer method is then flexible GMRES.
+int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
+  VecOp opL = [&](const double* in, double* out) { if (transpose) op_LT(c, in, out); else op_L(c, in, out); };
+  VecOp jac = [&](const double* in, double* out) { precond(c, transpose, in, out); };
+  if (c->pdelta < 0.0)
+    return gmres_core(c, opL, jac, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, nullptr, c->d_w,
+                      c->d_t1, c->d_t2, iters, relres);
+  VecOp opP = [&](const double* in, double* out) { if (transpose) op_PT(c, in, out); else op_P(c, in, out); };
+  VecOp inner = [&](const double* in, double* out) {
+    int it = 0;
+    double rr = 0;
+    (void)gmres_core(c, opP, jac, in, out, 1e-3, c->inner_iters, c->inner_iters, 1, true, c->d_Vin, nullptr,
+                     c->d_t4, c->d_t1, c->d_t5, &it, &rr);
+    c->inner_total += it;
+  };
+  return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
+                    c->d_t1, c->d_t2, iters, relres);
 }
 
 // ------------------------------------------------------------ device setup
@@ -494,6 +865,8 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_nptr, c->nptr.data(), (M + 1) * sizeof(int));
   up(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int));
   up(c->d_nrev, c->nrev.data(), c->nrev.size() * sizeof(int));
+  up(c->d_pptr, c->pptr.data(), (M + 1) * sizeof(int));
+  up(c->d_pidx, c->pidx.data(), c->pidx.size() * sizeof(int));
   up(c->d_ycr, ycr.data(), ycr.size() * sizeof(double));
   up(c->d_yce, yce.data(), yce.size() * sizeof(double));
   up(c->d_Cl, Cl.data(), Cl.size() * sizeof(double));
@@ -501,6 +874,23 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_ur, ur.data(), ur.size() * sizeof(double));
   up(c->d_kr, kr.data(), kr.size() * sizeof(double));
   up(c->d_dtab, dtab.data(), dtab.size() * sizeof(double));
+  if (c->fmm_order > 0) {
+    const int p1 = c->fmm_order + 1;
+    up(c->d_fA, c->tables.A.data(), c->tables.A.size() * sizeof(double));
+    up(c->d_fAL, c->tables.AL.data(), c->tables.AL.size() * sizeof(double));
+    up(c->d_fJ, c->tables.J.data(), c->tables.J.size() * sizeof(double));
+    up(c->d_fJoff, c->tables.Joff.data(), c->tables.Joff.size() * sizeof(int));
+    // sigma_l(kappa^2 r_i^2) up to degree p (normalisation of the sphere locals)
+    std::vector<double> sgp((size_t)M * (p1 + 1)), sgt(p1 + 2), qs(M);
+    for (int j = 0; j < M; ++j) {
+      host::bessel_sigma(p1, c->kappa * c->kappa * c->r[j] * c->r[j], sgt.data());
+      for (int l = 0; l <= p1; ++l) sgp[(size_t)j * (p1 + 1) + l] = sgt[l];
+      qs[j] = c->q[j] * std::sqrt(4.0 * host::kPi) / (c->eps1 * c->r[j]);  // charge as a degree-0 multipole at scale r_j
+    }
+    up(c->d_sgp, sgp.data(), sgp.size() * sizeof(double));
+    up(c->d_qsrc, qs.data(), qs.size() * sizeof(double));
+    c->nterms_p = host::sigma_terms(c->fmm_order, c->kappa * c->kappa * rmax * rmax);
+  }
   // Q: Q_r,j00 = q_j / sqrt(4 pi)
   std::vector<double> Qv((size_t)2 * M * c->L, 0.0);
   for (int j = 0; j < M; ++j) Qv[(size_t)j * c->L] = c->q[j] / std::sqrt(4.0 * host::kPi);
@@ -512,9 +902,34 @@ void upload_and_init(ddlpb_ctx* c) {
 }
 
 // grid fields and active point lists (depend on the centres)
+void upload_tree(ddlpb_ctx* c) {
+  const auto& t = c->tree;
+  auto up = [&](void* d, const void* h, size_t bytes) {
+    if (bytes) HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+  };
+  up(c->d_fcen, t.center.data(), t.center.size() * sizeof(double));
+  up(c->d_frad, t.radius.data(), t.radius.size() * sizeof(double));
+  up(c->d_fchild, t.child.data(), t.child.size() * sizeof(int));
+  up(c->d_fparent, t.parent.data(), t.parent.size() * sizeof(int));
+  up(c->d_flevn, t.level_nodes.data(), t.level_nodes.size() * sizeof(int));
+  up(c->d_sleaf, t.sphere_leaf.data(), t.sphere_leaf.size() * sizeof(int));
+  up(c->d_fm2lp, t.m2l_ptr.data(), t.m2l_ptr.size() * sizeof(int));
+  up(c->d_fm2ls, t.m2l_src.data(), t.m2l_src.size() * sizeof(int));
+  up(c->d_fm2ltp, t.m2lt_ptr.data(), t.m2lt_ptr.size() * sizeof(int));
+  up(c->d_fm2ltt, t.m2lt_tgt.data(), t.m2lt_tgt.size() * sizeof(int));
+  up(c->d_fnp, t.near_ptr.data(), t.near_ptr.size() * sizeof(int));
+  up(c->d_fni, t.near_idx.data(), t.near_idx.size() * sizeof(int));
+  hipLaunchKernelGGL(k_fmm_node_radial, dim3(nblk(t.nnodes, 128)), dim3(128), 0, c->stream, t.nnodes, c->fmm_order,
+                     c->kappa, c->d_frad, c->d_fkR, c->d_fiR);
+  HIPCHK(hipGetLastError());
+  c->stats.n_m2l = (int64_t)t.m2l_src.size();
+  c->stats.n_near_pairs = (int64_t)t.near_idx.size();
+}
+
 void geometry_on_device(ddlpb_ctx* c) {
   const int M = c->M, N = c->N;
   HIPCHK(hipMemcpyAsync(c->d_xyz, c->x.data(), 3 * M * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (c->fmm_order > 0) upload_tree(c);
   hipLaunchKernelGGL(k_grid_fields, dim3(nblk((long)M * N, 256)), dim3(256), 0, c->stream, M, N, c->d_xyz, c->d_rad,
                      c->d_leb, c->d_nptr, c->d_nidx, c->eta, c->d_f, c->d_U);
   hipLaunchKernelGGL(k_active_count, dim3(nblk(M, 128)), dim3(128), 0, c->stream, M, N, c->d_U, c->d_actcnt);
@@ -524,12 +939,25 @@ void geometry_on_device(ddlpb_ctx* c) {
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int i = 0; i < M; ++i) ptr[i + 1] = ptr[i] + cnt[i];
   c->nact = ptr[M];
+  c->near_pairs_pts = 0.0;
+  for (int i = 0; i < M; ++i) c->near_pairs_pts += (double)cnt[i] * (c->pptr[i + 1] - c->pptr[i]);
   HIPCHK(hipMemcpyAsync(c->d_actptr, ptr.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_cap_count, dim3(nblk(M, 128)), dim3(128), 0, c->stream, M, N, c->d_xyz, c->d_rad, c->d_leb,
+                     c->d_nptr, c->d_nidx, c->d_actcnt);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(cnt.data(), c->d_actcnt, M * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->ncap = 0;
+  for (int i = 0; i < M; ++i) c->ncap += cnt[i];
+  c->stats.n_cap_pairs = c->ncap;
   hipLaunchKernelGGL(k_active_fill, dim3(nblk(M, 128)), dim3(128), 0, c->stream, M, N, c->d_U, c->d_actptr,
                      c->d_actsph, c->d_actn);
   HIPCHK(hipGetLastError());
   c->stats.n_active_points = c->nact;
-  c->stats.n_near_pairs = (int64_t)M * M;
+  if (c->fmm_order == 0) c->stats.n_near_pairs = (int64_t)M * M;
+  c->near_pts_fmm = 0.0;
+  if (c->fmm_order > 0)
+    for (int i = 0; i < M; ++i) c->near_pts_fmm += (double)(ptr[i + 1] - ptr[i]) * (c->tree.near_ptr[i + 1] - c->tree.near_ptr[i]);
   c->rhs_ready = false;
 }
 
@@ -557,14 +985,25 @@ void compute_rhs(ddlpb_ctx* c) {
   const long MN = (long)c->M * c->N;
   fill(c, c->d_psi, MN, 0.0);
   fill(c, c->d_e, MN, 0.0);
-  if (c->nact > 0) {
+  if (c->nact > 0 && c->fmm_order == 0) {
+    KScope ks(c, "laplace_field", 16.0 * (double)c->nact * c->M);
     hipLaunchKernelGGL(k_laplace_field_direct, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->M, c->N, c->nact,
                        c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_psi,
                        c->d_e);
     HIPCHK(hipGetLastError());
+  } else if (c->nact > 0) {
+    {
+      KScope ks(c, "laplace_near", 16.0 * c->near_pts_fmm);
+      hipLaunchKernelGGL(k_laplace_field_list, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->N, c->nact,
+                         c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->d_fnp, c->d_fni, c->eps1,
+                         c->eps2, c->d_psi, c->d_e);
+      HIPCHK(hipGetLastError());
+    }
+    fmm_forward(c, 1, c->d_qsrc, 0, 1, c->d_SL);
+    l2p(c, 1, c->eps1 / c->eps2, c->d_psi, c->d_e);
   }
   moments(c, nullptr, c->d_e, nullptr, c->d_m);
-  sl_field(c, c->d_m, false, 0, c->d_Phi);
+  sl_field_full(c, c->d_m, c->d_Phi);
   apply_LX(c, nullptr, 0.0, nullptr, 0.0, c->d_psi, c->d_Phi, c->d_Phi, -1.0, c->d_g);
   c->rhs_ready = true;
 }
@@ -600,7 +1039,7 @@ int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, con
     c->lmax = lmax;
     c->L = (lmax + 1) * (lmax + 1);
     c->LP = (lmax + 2) * (lmax + 2);
-    c->LY = c->LP;
+    c->LY = std::max(c->LP, (fmm_order + 1) * (fmm_order + 1));
     c->LUR = lmax + 2;
     c->N = n_lebedev;
     c->rule = host::lebedev_rule(n_lebedev);
@@ -611,6 +1050,13 @@ int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, con
     c->q.assign(charges, charges + n_atoms);
     int r2 = build_neighbours(c);
     if (r2) { delete c; return r2; }
+    build_pairs(c, c->pdelta, c->pptr, c->pidx);
+    if (fmm_order > 0) {
+      if (fmm_order < lmax + 1) { delete c; return DDLPB_EINVAL; }
+      fmm::build_tables(fmm_order, c->tables);
+      fmm::build_tree(c->M, c->x.data(), c->r.data(), c->tree);
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+    }
     c->stats.fmm_order = fmm_order;
     c->stats.fmm_order_below_lmax = (fmm_order > 0 && fmm_order < lmax) ? 1 : 0;
     *out = c;
@@ -630,6 +1076,7 @@ int ddlpb_solve(ddlpb_ctx* c, double tol, double* energy_out) {
     t0 = std::chrono::steady_clock::now();
     int it = 0;
     double rel = 0;
+    if (!c->warm_start) fill(c, c->d_X, 2L * c->M * c->L, 0.0);
     rc = gmres(c, false, c->d_g, c->d_X, tol, &it, &rel);
     c->stats.iters_primal = it;
     c->stats.resid_primal = rel;
@@ -638,6 +1085,7 @@ int ddlpb_solve(ddlpb_ctx* c, double tol, double* energy_out) {
     double E = 0;
     HIPCHK(hipMemcpyAsync(&E, c->d_scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    ktimer_flush(c);
     c->stats.ms_primal = elapsed_ms(t0);
     c->energy = E;
     if (energy_out) *energy_out = E;
@@ -653,10 +1101,12 @@ int ddlpb_adjoint(ddlpb_ctx* c, double tol) {
     auto t0 = std::chrono::steady_clock::now();
     int it = 0;
     double rel = 0;
+    if (!c->warm_start) fill(c, c->d_Xa, 2L * c->M * c->L, 0.0);
     int rc = gmres(c, true, c->d_Q, c->d_Xa, tol, &it, &rel);
     HIPCHK(hipStreamSynchronize(c->stream));
     c->stats.iters_adjoint = it;
     c->stats.resid_adjoint = rel;
+    ktimer_flush(c);
     c->stats.ms_adjoint = elapsed_ms(t0);
     c->state = 2;
     return rc;
@@ -675,14 +1125,34 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
     syn2(c, c->d_Xa, 1, c->d_cg, nullptr);
     // h = e + Syn(y(X)), m = C (.) An(U h), Phi = Phi[m] (full)
     moments(c, c->d_X, c->d_e, c->d_h, c->d_m);
-    sl_field(c, c->d_m, false, 0, c->d_Phi);
+    sl_field_full(c, c->d_m, c->d_Phi);
     // lambda' (other spheres only, degree lmax+1) and eta = Syn(C (.) lambda)
-    sl_adjoint(c, c->d_cg, c->lmax + 1, 1, c->d_lam);
+    sl_adjoint_full(c, c->d_cg, c->lmax + 1, 1, c->LP, c->d_lam);
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eta<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->LY, c->d_Y,
                                             c->d_cg, c->d_lam, c->LP, c->d_Cl, c->LUR, c->d_eta));
     HIPCHK(hipGetLastError());
-    // grad Phi' at active points
-    if (c->nact > 0) sl_field(c, c->d_m, true, 1, c->d_gphi);
+    const bool fmmode = c->fmm_order > 0;
+    // grad Phi' at active points (near part by pairs, far part from the sphere locals)
+    if (c->nact > 0) {
+      if (!fmmode) {
+        sl_field(c, c->d_m, true, 1, c->d_gphi);
+      } else {
+        KScope ks(c, "sl_near_grad", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
+        LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
+                                                c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
+                                                c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_ur, c->LUR,
+                                                c->kappa, 1, 0, c->d_gphi));
+        HIPCHK(hipGetLastError());
+      }
+      if (fmmode) {
+        fmm_forward(c, 0, c->d_m, c->lmax, c->L, c->d_SL);
+        P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_grad_yuk<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
+                                                    c->stream, c->nact, c->d_actsph, c->d_actn, c->d_rad, c->d_leb,
+                                                    c->d_sgp, c->fmm_order + 2, c->kappa, c->nterms_p, c->d_SL,
+                                                    c->d_gphi));
+        HIPCHK(hipGetLastError());
+      }
+    }
     // switching / near-field terms
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_force_switch<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->d_leb,
                                             c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U, c->d_sgr,
@@ -694,14 +1164,41 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
     if (c->nact > 0) {
       hipLaunchKernelGGL(k_force_points, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, M, N, c->nact,
                          c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U,
-                         c->d_xr, c->d_xe, c->d_eta, c->d_gphi, 1, c->d_fpt);
+                         c->d_xr, c->d_xe, c->d_eta, c->d_gphi, fmmode ? 0 : 1, c->d_fpt);
+      HIPCHK(hipGetLastError());
+      if (fmmode) {
+        hipLaunchKernelGGL(k_force_points_lap_list, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, N, c->nact,
+                           c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U,
+                           c->d_xr, c->d_eta, c->d_fnp, c->d_fni, c->d_fpt);
+        fmm_forward(c, 1, c->d_qsrc, 0, 1, c->d_SL);
+        P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_force_lap<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
+                                                    c->stream, N, c->nact, c->d_actsph, c->d_actn, c->d_rad,
+                                                    c->d_leb, c->d_U, c->d_xr, c->d_eta, c->eps1, c->eps2, c->d_SL,
+                                                    c->d_fpt));
+        HIPCHK(hipGetLastError());
+      }
       hipLaunchKernelGGL(k_sum_points, dim3(M), dim3(256), 0, c->stream, M, c->d_actptr, c->d_fpt, c->d_fpts);
       HIPCHK(hipGetLastError());
     }
     // source-side terms
-    hipLaunchKernelGGL(k_force_laplace_source, dim3(M), dim3(256), 0, c->stream, M, N, c->nact, c->d_actsph,
-                       c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta,
-                       c->d_flsrc);
+    if (!fmmode) {
+      hipLaunchKernelGGL(k_force_laplace_source, dim3(M), dim3(256), 0, c->stream, M, N, c->nact, c->d_actsph,
+                         c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta,
+                         c->d_flsrc);
+    } else {
+      fill(c, c->d_flsrc, 3L * M, 0.0);
+      hipLaunchKernelGGL(k_force_laplace_source_list, dim3(M), dim3(256), 0, c->stream, N, c->d_actptr, c->d_actn,
+                         c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta, c->d_fnp,
+                         c->d_fni, c->d_flsrc);
+      hipLaunchKernelGGL(k_lap_src_grids, dim3(nblk((long)M * N, 256)), dim3(256), 0, c->stream, M, N, c->d_leb,
+                         c->d_U, c->d_xr, c->d_eta, c->eps1, c->eps2, c->d_zr, c->d_ze);
+      HIPCHK(hipGetLastError());
+      p2l_dual(c, c->d_zr, c->d_ze, c->d_Lam);
+      fmm_transpose(c, 1, c->d_Lam, 1, 4, 0, c->d_tmp4);
+      hipLaunchKernelGGL(k_force_lap_far_source, dim3(nblk(M, 256)), dim3(256), 0, c->stream, M, 4, c->d_q, c->d_rad,
+                         c->d_tmp4, c->d_flsrc);
+      HIPCHK(hipGetLastError());
+    }
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_force_yukawa_source<LMc>), dim3(M), dim3(128), 0, c->stream, M,
                                             c->d_m, c->d_lam, c->d_dtab, c->d_kr, c->LUR, c->kappa, c->d_fysrc));
     hipLaunchKernelGGL(k_force_final, dim3(nblk(M, 256)), dim3(256), 0, c->stream, M, c->d_nptr, c->d_nidx,
@@ -710,6 +1207,7 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
     HIPCHK(hipMemcpyAsync(forces_out, c->d_F, 3L * M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     (void)MN;
+    ktimer_flush(c);
     c->stats.ms_forces = elapsed_ms(t0);
     return DDLPB_OK;
   });
@@ -718,6 +1216,8 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
 void ddlpb_free(ddlpb_ctx* c) {
   if (!c) return;
   if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+  for (auto& p : c->ev_pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -741,6 +1241,19 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "inner_sweeps") {
     if (!(v >= 0 && v <= 64)) return DDLPB_EINVAL;
     c->sweeps = (int)v;
+  } else if (k == "precond_delta") {
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v < 0 || v <= 20.0)) return DDLPB_EINVAL;
+    c->pdelta = v;
+    build_pairs(c, c->pdelta, c->pptr, c->pidx);
+  } else if (k == "inner_iters") {
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v >= 1 && v <= 200)) return DDLPB_EINVAL;
+    c->inner_iters = (int)v;
+  } else if (k == "kernel_timing") {
+    c->ktiming = v != 0;
+  } else if (k == "warm_start") {
+    c->warm_start = v != 0;
   } else if (k == "max_iter") {
     if (!(v >= 1 && v <= 1e6)) return DDLPB_EINVAL;
     c->maxit = (int)v;
@@ -768,13 +1281,17 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
     c->x.assign(centers, centers + 3L * c->M);
     int rc = build_neighbours(c);
     if (rc) { c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; return rc; }
+    build_pairs(c, c->pdelta, c->pptr, c->pidx);
     if (c->dev_ready) {
-      if (c->nidx.size() != onidx.size()) {
-        // neighbour count changed: the workspace layout changes, rebuild the device state
+      const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap;
+      if (relayout) {
+        // list capacities exceeded: the workspace layout changes; keep X and X_adj
         std::vector<double> X(2L * c->M * c->L), Xa(2L * c->M * c->L);
         HIPCHK(hipMemcpyAsync(X.data(), c->d_X, X.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(Xa.data(), c->d_Xa, Xa.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        c->nnz_cap = c->nidx.size() + c->nidx.size() / 4 + 64;
+        c->pnz_cap = c->pidx.size() + c->pidx.size() / 4 + 64;
         size_t need = workspace_size(c);
         if (c->ws_bound && need > c->ws_bytes) return DDLPB_ENOMEM;
         if (c->ws_owned && need > c->ws_bytes) {
@@ -790,9 +1307,14 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
         HIPCHK(hipMemcpyAsync(c->d_X, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(c->d_Xa, Xa.data(), Xa.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
       } else {
-        HIPCHK(hipMemcpyAsync(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(c->d_nrev, c->nrev.data(), c->nrev.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(c->d_nptr, c->nptr.data(), (c->M + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        auto up = [&](void* d, const void* h, size_t bytes) {
+          if (bytes) HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+        };
+        up(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int));
+        up(c->d_nrev, c->nrev.data(), c->nrev.size() * sizeof(int));
+        up(c->d_nptr, c->nptr.data(), (c->M + 1) * sizeof(int));
+        up(c->d_pidx, c->pidx.data(), c->pidx.size() * sizeof(int));
+        up(c->d_pptr, c->pptr.data(), (c->M + 1) * sizeof(int));
       }
       geometry_on_device(c);
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -837,6 +1359,26 @@ const char* ddlpb_strerror(int code) {
   int k = -code;
   if (k < 0 || k > 6) return "unknown error";
   return kErr[k];
+}
+
+int ddlpb_kernel_times(ddlpb_ctx* c, int32_t idx, char* name_out, double* ms, int64_t* launches, double* work) {
+  if (!c || idx < 0) return DDLPB_EINVAL;
+  if (idx >= (int)c->ktimers.size()) return DDLPB_EINVAL;
+  const auto& t = c->ktimers[idx];
+  if (name_out) { std::strncpy(name_out, t.name.c_str(), 63); name_out[63] = 0; }
+  if (ms) *ms = t.ms;
+  if (launches) *launches = t.launches;
+  if (work) *work = t.work;
+  return DDLPB_OK;
+}
+
+int ddlpb_kernel_times_reset(ddlpb_ctx* c) {
+  if (!c) return DDLPB_EINVAL;
+  return guarded([&]() -> int {
+    ktimer_flush(c);
+    for (auto& t : c->ktimers) { t.ms = 0; t.work = 0; t.launches = 0; }
+    return DDLPB_OK;
+  });
 }
 
 int ddlpb_get_grid(ddlpb_ctx* c, double* f_out, double* u_out) {

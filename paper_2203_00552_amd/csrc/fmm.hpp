@@ -1,0 +1,579 @@
+// Fast multipole method on the device (Appendix): translations of the screened
+// Coulomb (Yukawa) and Coulomb (Laplace) expansions between tree nodes.
+//
+// Scaled bases about a centre c with scale R (the node radius):
+//   Yukawa   multipole  k_l(kappa|v|)/k_l(kappa R) Y_lm(v/|v|),   local  i_l(kappa|v|)/i_l(kappa R) Y_lm
+//   Laplace  multipole  (R/|v|)^(l+1) Y_lm(v/|v|),               local  (|v|/R)^l Y_lm
+// A leaf is one sphere (centre x_j, scale r_j), so the sphere's own expansions are
+// the leaf expansions.  Every translation rotates the frame so that the target
+// centre lies on the negative z axis of the source centre (three z-rotations and
+// two applications of the fixed 90-degree rotation J), applies the translation
+// along z (Appendix formulas for Yukawa; their kappa -> 0 limits for Laplace)
+// and rotates back.  The adjoint passes apply exact transposes.
+//
+// One 64-lane wavefront (one block) performs one translation at a time with its
+// vectors in LDS.
+#pragma once
+#include "device_math.hpp"
+
+namespace ddlpb {
+
+constexpr int kPmaxFmm = 20;
+constexpr int kPFmm = (kPmaxFmm + 1) * (kPmaxFmm + 1);
+
+struct FmmDev {
+  int kernel;            // 0 Yukawa, 1 Laplace
+  int p;                 // expansion order of the tree
+  double kappa;
+  const double* A;       // Yukawa coefficients [P1][P1][P1][P1]
+  const double* AL;      // Laplace coefficients [3][P1][P1][P1]
+  const double* J;       // packed J_l blocks
+  const int* Joff;
+  const double* center;  // [nn][3]
+  const double* radius;  // [nn]
+  const double* kR;      // [nn][P1]: k_l(kappa R_node)
+  const double* iR;      // [nn][P1]: i_l(kappa R_node)
+};
+
+struct TransScratch {
+  double b0[kPFmm], b1[kPFmm];
+  double bes[2 * kPmaxFmm + 4];
+  double pw1[2 * kPmaxFmm + 4], pw2[2 * kPmaxFmm + 4];
+  double radS[kPmaxFmm + 2], radT[kPmaxFmm + 2];
+  double ang[4];
+};
+
+__device__ __forceinline__ void zrot_inplace(double* c, int pdeg, double alpha) {
+  // c'_m = c_m cos(m a) - c_-m sin(m a), c'_-m = c_m sin(m a) + c_-m cos(m a)
+  const int npairs = pdeg * (pdeg + 1) / 2;  // (l, m>0) pairs
+  for (int t = threadIdx.x; t < npairs; t += blockDim.x) {
+    int l = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5) + 1;
+    while (l * (l - 1) / 2 > t) --l;
+    while ((l + 1) * l / 2 <= t) ++l;
+    const int m = t - l * (l - 1) / 2 + 1;
+    double s, co;
+    sincos(m * alpha, &s, &co);
+    const double a = c[lmi(l, m)], b = c[lmi(l, -m)];
+    c[lmi(l, m)] = a * co - b * s;
+    c[lmi(l, -m)] = a * s + b * co;
+  }
+}
+
+// out = J in (trans = 0) or J^T in (trans = 1), block-diagonal in l
+__device__ __forceinline__ void japply(const FmmDev& f, const double* in, double* out, int pdeg, int trans) {
+  const int n = (pdeg + 1) * (pdeg + 1);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int l = (int)sqrt((double)t + 0.5);
+    const int mo = t - l * l - l;
+    const int w = 2 * l + 1;
+    const double* Jl = f.J + f.Joff[l];
+    double s = 0.0;
+    for (int mi = -l; mi <= l; ++mi) {
+      const double jv = trans ? Jl[(mi + l) * w + (mo + l)] : Jl[(mo + l) * w + (mi + l)];
+      s += jv * in[lmi(l, mi)];
+    }
+    out[t] = s;
+  }
+}
+
+// sigma_n(z2) = i_n(z)/z^n for n = 0..nmax (series at the top, downward recurrence); lane 0 only
+__device__ __forceinline__ void sigma_all(double z2, int nmax, double* sg) {
+  double top[2];
+  for (int q = 0; q < 2; ++q) {
+    const int l = nmax + 1 - q;
+    double df = 1.0;
+    for (int k = 2 * l + 1; k > 1; k -= 2) df *= k;
+    double term = 1.0 / df, sum = term;
+    for (int k = 0; k < 200; ++k) {
+      term *= z2 * 0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
+      sum += term;
+      if (term < 1e-18 * sum) break;
+    }
+    top[q] = sum;
+  }
+  double sp1 = top[0];
+  sg[nmax] = top[1];
+  for (int l = nmax; l >= 1; --l) {
+    const double s = z2 * sp1 + (2.0 * l + 1.0) * sg[l];
+    sp1 = sg[l];
+    sg[l - 1] = s;
+  }
+}
+// k_n(z) for n = 0..nmax (upward recurrence); lane 0 only
+__device__ __forceinline__ void kbes_all(double z, int nmax, double* k) {
+  const double e = exp(-z);
+  k[0] = 1.5707963267948966 * e / z;
+  if (nmax >= 1) k[1] = 1.5707963267948966 * e * (z + 1.0) / (z * z);
+  for (int l = 1; l < nmax; ++l) k[l + 1] = k[l - 1] + (2.0 * l + 1.0) / z * k[l];
+}
+
+// Translation (kind 0 M2M, 1 M2L, 2 L2L) from node S to node T of the expansion in
+// sc.b0 (degree ps; degree pt when transposed); the result is added to acc
+// (degree pt; ps when transposed).  All lanes of the block must call it.
+__device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int pt, int transposed, TransScratch& sc,
+                          double* acc) {
+  if (threadIdx.x == 0) {
+    double d[3], rho2 = 0.0;
+    for (int a = 0; a < 3; ++a) { d[a] = f.center[3 * T + a] - f.center[3 * S + a]; rho2 += d[a] * d[a]; }
+    double rho = sqrt(rho2);
+    double th = 0.0, ph = 0.0;
+    if (rho > 1e-12) {
+      th = acos(fmin(1.0, fmax(-1.0, d[2] / rho)));
+      ph = atan2(d[1], d[0]);
+    } else {
+      rho = 1e-12;
+    }
+    sc.ang[0] = th; sc.ang[1] = ph; sc.ang[2] = rho;
+    const double RS = f.radius[S], RT = f.radius[T];
+    const int nmax = ps + pt;
+    if (f.kernel == 0) {
+      const double z = f.kappa * rho;
+      if (kind == 1) {
+        kbes_all(z, nmax, sc.bes);
+        double iz = 1.0;  // (-z)^-k
+        for (int k = 0; k <= nmax; ++k) { sc.pw1[k] = iz; iz *= -1.0 / z; }
+      } else {
+        sigma_all(z * z, nmax, sc.bes);
+        double zp = 1.0;
+        for (int k = 0; k <= nmax; ++k) { sc.pw1[k] = zp; zp *= z; }
+      }
+      for (int l = 0; l <= ps; ++l) sc.radS[l] = (kind == 2) ? 1.0 / f.iR[S * (f.p + 1) + l] : 1.0 / f.kR[S * (f.p + 1) + l];
+      for (int l = 0; l <= pt; ++l) sc.radT[l] = (kind == 0) ? f.kR[T * (f.p + 1) + l] : f.iR[T * (f.p + 1) + l];
+    } else {
+      // powers of the ratios of the Laplace translations
+      double a1, a2;
+      if (kind == 0) { a1 = RS / RT; a2 = rho / RT; }        // (RS/RT)^(l+1) (rho/RT)^(l'-l)
+      else if (kind == 1) { a1 = RT / rho; a2 = RS / rho; }  // (RT/rho)^l' (RS/rho)^(l+1)
+      else { a1 = RT / RS; a2 = rho / RS; }                  // (RT/RS)^l' (rho/RS)^(l-l')
+      double v1 = 1.0, v2 = 1.0;
+      for (int k = 0; k <= nmax + 1; ++k) { sc.pw1[k] = v1; sc.pw2[k] = v2; v1 *= a1; v2 *= a2; }
+    }
+  }
+  __syncthreads();
+  const double th = sc.ang[0], ph = sc.ang[1];
+  const int pin = transposed ? pt : ps, pout = transposed ? ps : pt;
+  // rotate the input to the frame where the target sits on the -z axis
+  zrot_inplace(sc.b0, pin, -ph);
+  __syncthreads();
+  japply(f, sc.b0, sc.b1, pin, 0);
+  __syncthreads();
+  zrot_inplace(sc.b1, pin, 3.141592653589793 - th);
+  __syncthreads();
+  japply(f, sc.b1, sc.b0, pin, 1);
+  __syncthreads();
+  // translation along z
+  const int P1 = f.p + 1;
+  const int nout = (pout + 1) * (pout + 1);
+  for (int t = threadIdx.x; t < nout; t += blockDim.x) {
+    const int lo = (int)sqrt((double)t + 0.5);
+    const int m = t - lo * lo - lo, am = abs(m);
+    double s = 0.0;
+    for (int li = am; li <= pin; ++li) {
+      const int l = transposed ? lo : li;   // source degree
+      const int lp = transposed ? li : lo;  // target degree
+      double e;
+      if (f.kernel == 0) {
+        const double* Ar = f.A + (((size_t)l * P1 + lp) * P1 + am) * P1;
+        double sk = 0.0;
+        const int kmax = min(l, lp);
+        if (kind == 1) {
+          for (int k = am; k <= kmax; ++k) sk += Ar[k] * sc.bes[l + lp - k] * sc.pw1[k];
+          e = sk * sc.radT[lp] * sc.radS[l] * ((l & 1) ? -1.0 : 1.0);
+        } else {
+          for (int k = am; k <= kmax; ++k) sk += Ar[k] * sc.bes[l + lp - k] * sc.pw1[l + lp - 2 * k];
+          e = sk * sc.radT[lp] * sc.radS[l] * ((kind == 2 && ((l + lp) & 1)) ? -1.0 : 1.0);
+        }
+      } else {
+        const double a = f.AL[(size_t)kind * P1 * P1 * P1 + ((size_t)l * P1 + lp) * P1 + am];
+        if (a == 0.0) continue;
+        if (kind == 0) e = a * sc.pw1[l + 1] * sc.pw2[lp - l];
+        else if (kind == 1) e = a * sc.pw1[lp] * sc.pw2[l + 1];
+        else e = a * sc.pw1[lp] * sc.pw2[l - lp];
+      }
+      s += e * sc.b0[lmi(li, m)];
+    }
+    sc.b1[t] = s;
+  }
+  __syncthreads();
+  // rotate back
+  japply(f, sc.b1, sc.b0, pout, 0);
+  __syncthreads();
+  zrot_inplace(sc.b0, pout, th - 3.141592653589793);
+  __syncthreads();
+  japply(f, sc.b0, sc.b1, pout, 1);
+  __syncthreads();
+  zrot_inplace(sc.b1, pout, ph);
+  __syncthreads();
+  for (int t = threadIdx.x; t < nout; t += blockDim.x) acc[t] += sc.b1[t];
+  __syncthreads();
+}
+
+// per-node Bessel scales k_l(kappa R), i_l(kappa R), l = 0..p
+__global__ void k_fmm_node_radial(int nn, int p, double kappa, const double* __restrict__ radius, double* __restrict__ kR,
+                                  double* __restrict__ iR) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const double z = kappa * radius[n];
+  double sg[kPmaxFmm + 2], kk[kPmaxFmm + 2];
+  sigma_all(z * z, p, sg);
+  kbes_all(z, p, kk);
+  double zl = 1.0;
+  for (int l = 0; l <= p; ++l) {
+    kR[n * (p + 1) + l] = kk[l];
+    iR[n * (p + 1) + l] = sg[l] * zl;
+    zl *= z;
+  }
+}
+
+// leaf expansions from per-sphere coefficients (degree ps, row stride lds), zero padded to degree p
+__global__ void k_fmm_leaf_set(int M, int p, int ps, int lds, const int* __restrict__ sphere_leaf,
+                               const double* __restrict__ src, double* __restrict__ E) {
+  const int j = blockIdx.x;
+  const int P = (p + 1) * (p + 1), Ps = (ps + 1) * (ps + 1);
+  double* e = E + (long)sphere_leaf[j] * P;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) e[t] = t < Ps ? src[(long)j * lds + t] : 0.0;
+}
+// per-sphere coefficients (degree pd, row stride ldd) from leaf expansions; accumulate or overwrite
+__global__ void k_fmm_leaf_get(int M, int p, int pd, int ldd, const int* __restrict__ sphere_leaf,
+                               const double* __restrict__ E, int accumulate, double* __restrict__ dst) {
+  const int j = blockIdx.x;
+  const int P = (p + 1) * (p + 1), Pd = (pd + 1) * (pd + 1);
+  const double* e = E + (long)sphere_leaf[j] * P;
+  for (int t = threadIdx.x; t < Pd; t += blockDim.x) {
+    const double v = t < P ? e[t] : 0.0;
+    dst[(long)j * ldd + t] = accumulate ? dst[(long)j * ldd + t] + v : v;
+  }
+}
+
+// upward pass of one level: M[n] = sum_children M2M(child -> n) M[child]  (internal nodes only)
+__global__ __launch_bounds__(64) void k_fmm_upward(FmmDev f, const int* __restrict__ nodes, int count,
+                                                   const int* __restrict__ child, double* __restrict__ E) {
+  __shared__ TransScratch sc;
+  __shared__ double acc[kPFmm];
+  const int n = nodes[blockIdx.x];
+  if (child[2 * n] < 0) return;  // leaf: already set (uniform for the block)
+  const int P = (f.p + 1) * (f.p + 1);
+  for (int t = threadIdx.x; t < P; t += blockDim.x) acc[t] = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    const int ch = child[2 * n + c];
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
+    __syncthreads();
+    translate(f, 0, ch, n, f.p, f.p, 0, sc, acc);
+  }
+  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] = acc[t];
+}
+
+// multipole-to-local: L[T] = sum_{S in list(T)} M2L(S -> T) M[S]  (every node, lists by target)
+// transposed: Mu[S] = sum_{T in list^T(S)} M2L(S -> T)^T Lambda[T]  (lists by source)
+__global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __restrict__ lptr,
+                                                const int* __restrict__ lidx, int transposed,
+                                                const double* __restrict__ Ein, double* __restrict__ Eout) {
+  __shared__ TransScratch sc;
+  __shared__ double acc[kPFmm];
+  const int P = (f.p + 1) * (f.p + 1);
+  for (int n = blockIdx.x; n < nn; n += gridDim.x) {
+    for (int t = threadIdx.x; t < P; t += blockDim.x) acc[t] = 0.0;
+    for (int q = lptr[n]; q < lptr[n + 1]; ++q) {
+      const int o = lidx[q];
+      __syncthreads();
+      for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = Ein[(long)o * P + t];
+      __syncthreads();
+      if (!transposed) translate(f, 1, o, n, f.p, f.p, 0, sc, acc);
+      else translate(f, 1, n, o, f.p, f.p, 1, sc, acc);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += blockDim.x) Eout[(long)n * P + t] = acc[t];
+    __syncthreads();
+  }
+}
+
+// downward pass of one level: L[n] += L2L(parent -> n) L[parent]
+// transposed downward (adjoint of the upward pass): Mu[n] += M2M(n -> parent)^T Mu[parent]
+__global__ __launch_bounds__(64) void k_fmm_downward(FmmDev f, const int* __restrict__ nodes, int count,
+                                                     const int* __restrict__ parent, int transposed,
+                                                     double* __restrict__ E) {
+  __shared__ TransScratch sc;
+  __shared__ double acc[kPFmm];
+  const int n = nodes[blockIdx.x];
+  const int par = parent[n];
+  if (par < 0) return;
+  const int P = (f.p + 1) * (f.p + 1);
+  for (int t = threadIdx.x; t < P; t += blockDim.x) { acc[t] = 0.0; sc.b0[t] = E[(long)par * P + t]; }
+  __syncthreads();
+  if (!transposed) translate(f, 2, par, n, f.p, f.p, 0, sc, acc);
+  else translate(f, 0, n, par, f.p, f.p, 1, sc, acc);
+  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
+}
+
+// transposed upward pass of one level (adjoint of the downward pass):
+// Lambda[n] += sum_children L2L(n -> child)^T Lambda[child]
+__global__ __launch_bounds__(64) void k_fmm_upward_T(FmmDev f, const int* __restrict__ nodes, int count,
+                                                     const int* __restrict__ child, double* __restrict__ E) {
+  __shared__ TransScratch sc;
+  __shared__ double acc[kPFmm];
+  const int n = nodes[blockIdx.x];
+  if (child[2 * n] < 0) return;
+  const int P = (f.p + 1) * (f.p + 1);
+  for (int t = threadIdx.x; t < P; t += blockDim.x) acc[t] = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    const int ch = child[2 * n + c];
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
+    __syncthreads();
+    translate(f, 2, n, ch, f.p, f.p, 1, sc, acc);
+  }
+  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
+}
+
+}  // namespace ddlpb
+
+namespace ddlpb {
+
+// ---------------------------------------------------- sphere <-> grid glue
+// Far field at the active points from the sphere locals SL [M][P] (scale r_i: a local
+// evaluated on its own sphere has radial factor 1):
+//   mode 0 (Yukawa):  out1 += sum SL Y(s_n)
+//   mode 1 (Laplace): out1 += sum SL Y(s_n),  out2 += c2 sum (l / r_i) SL Y(s_n)  (normal derivative)
+__global__ __launch_bounds__(256) void k_l2p(int nact, int N, int P, int LY, const int* __restrict__ act_sph,
+                                             const int* __restrict__ act_n, const double* __restrict__ rad,
+                                             const double* __restrict__ Y, const double* __restrict__ SL, int mode,
+                                             double c2, double* __restrict__ out1, double* __restrict__ out2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  const double* Yn = Y + (long)n * LY;
+  const double* s = SL + (long)i * P;
+  double v = 0.0, dn = 0.0;
+  int l = 0;
+  for (int t = 0; t < P; ++t) {
+    if ((l + 1) * (l + 1) <= t) ++l;
+    const double a = Yn[t] * s[t];
+    v += a;
+    dn += l * a;
+  }
+  const long in = (long)i * N + n;
+  out1[in] += v;
+  if (mode == 1) out2[in] += c2 * dn / rad[i];
+}
+
+// Dual of the grid evaluation: Lam_i,lm = sum_n (g1_in + (l/r_i) g2_in) Y_lm(s_n), l <= p
+__global__ __launch_bounds__(256) void k_p2l_dual(int M, int N, int P, int LY, const double* __restrict__ rad,
+                                                  const double* __restrict__ Y, const double* __restrict__ g1,
+                                                  const double* __restrict__ g2, double* __restrict__ Lam) {
+  __shared__ double a[kMaxN], b[kMaxN];
+  const int i = blockIdx.x;
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    a[n] = g1[(long)i * N + n];
+    b[n] = g2 ? g2[(long)i * N + n] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < P; t += blockDim.x) {
+    const int l = (int)sqrt((double)t + 0.5);
+    const double sl = l / rad[i];
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) s += (a[n] + sl * b[n]) * Y[(long)n * LY + t];
+    Lam[(long)i * P + t] = s;
+  }
+}
+
+// Vacuum field by listed pairs (near part): psi += sum q_k/(eps1 d), e += (1/eps2) sum d_n(q_k / d)
+__global__ __launch_bounds__(256) void k_laplace_field_list(int N, int nact, const int* __restrict__ act_sph,
+                                                            const int* __restrict__ act_n, const double* __restrict__ xyz,
+                                                            const double* __restrict__ rad, const double* __restrict__ leb,
+                                                            const double* __restrict__ q, const int* __restrict__ lptr,
+                                                            const int* __restrict__ lidx, double eps1, double eps2,
+                                                            double* __restrict__ psi_out, double* __restrict__ e_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  double p[3], s[3];
+  for (int a = 0; a < 3; ++a) { s[a] = leb[4 * n + a]; p[a] = xyz[3 * i + a] + rad[i] * s[a]; }
+  double psi = 0.0, dn = 0.0;
+  for (int t = lptr[i]; t < lptr[i + 1]; ++t) {
+    const int j = lidx[t];
+    const double vx = p[0] - xyz[3 * j], vy = p[1] - xyz[3 * j + 1], vz = p[2] - xyz[3 * j + 2];
+    const double id = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+    const double qi = q[j] * id;
+    psi += qi;
+    dn -= qi * id * id * (vx * s[0] + vy * s[1] + vz * s[2]);
+  }
+  const long in = (long)i * N + n;
+  psi_out[in] += psi / eps1;
+  e_out[in] += dn / eps2;
+}
+
+// Gradient (w.r.t. the point) of the far single-layer field from the Yukawa sphere local
+// sum_lm SL_ilm i_l(kappa|v|)/i_l(kappa r_i) Y_lm(v), v = x - x_i, at every active point;
+// added to gphi [nact][3].
+template <int PD>
+__global__ __launch_bounds__(128) void k_local_grad_yuk(int nact, const int* __restrict__ act_sph,
+                                                        const int* __restrict__ act_n, const double* __restrict__ rad,
+                                                        const double* __restrict__ leb, const double* __restrict__ iR_s,
+                                                        int ldi, double kappa, int nterms,
+                                                        const double* __restrict__ SL, double* __restrict__ gphi) {
+  constexpr int P = (PD + 1) * (PD + 1);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  using D = Dual<double>;
+  const double ri = rad[i], iri = 1.0 / ri;
+  D v[3];
+  for (int a = 0; a < 3; ++a) { v[a] = D(leb[4 * n + a]); v[a].g[a] = iri; }  // v = (x - x_i)/r_i, dv/dx = 1/r_i
+  D z2 = (kappa * kappa * ri * ri) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  D sg[PD + 1];
+  sigma_weights<PD, D>(z2, nterms, sg);
+  const double* s = SL + (long)i * P;
+  D part[PD + 1];
+#pragma unroll
+  for (int l = 0; l <= PD; ++l) part[l] = D(0.0);
+  for_each_solid_harmonic<PD, D>(v[0], v[1], v[2], [&](int l, int idx, const D& S) { part[l] = part[l] + s[idx] * S; });
+  D acc(0.0);
+#pragma unroll
+  for (int l = 0; l <= PD; ++l) acc = acc + (1.0 / iR_s[(long)i * ldi + l]) * (sg[l] * part[l]);
+  for (int a = 0; a < 3; ++a) gphi[3L * k + a] += acc.g[a];
+}
+
+// Laplace far-field target terms at every active point from the sphere local of the
+// vacuum field (value scale r_i): out[k] += c (xi_r grad psi + eta (eps1/eps2) grad (s . grad psi)),
+// c = -1/2 w U; uses nested dual numbers for the Hessian.
+template <int PD>
+__global__ __launch_bounds__(128) void k_local_force_lap(int N, int nact, const int* __restrict__ act_sph,
+                                                         const int* __restrict__ act_n, const double* __restrict__ rad,
+                                                         const double* __restrict__ leb, const double* __restrict__ U,
+                                                         const double* __restrict__ xr, const double* __restrict__ etag,
+                                                         double eps1, double eps2, const double* __restrict__ SL,
+                                                         double* __restrict__ fpt) {
+  constexpr int P = (PD + 1) * (PD + 1);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  const long in = (long)i * N + n;
+  using D = Dual<double>;
+  using DD = Dual<D>;
+  const double ri = rad[i], iri = 1.0 / ri;
+  const double s[3] = {leb[4 * n], leb[4 * n + 1], leb[4 * n + 2]};
+  DD v[3];
+  for (int a = 0; a < 3; ++a) {
+    D inner(s[a]);
+    inner.g[a] = iri;  // inner derivative: gradient
+    v[a] = DD(inner);
+    D og(0.0);
+    og.v = iri;        // outer derivative along axis a, value part
+    for (int b = 0; b < 3; ++b) v[a].g[b] = D(0.0);
+    v[a].g[a] = og;
+  }
+  const double* sl = SL + (long)i * P;
+  DD acc(D(0.0));
+  for_each_solid_harmonic<PD, DD>(v[0], v[1], v[2], [&](int l, int idx, const DD& S) { acc = acc + D(sl[idx]) * S; });
+  // acc.g[a].v = d psi / dx_a ; acc.g[a].g[b] = d2 psi / dx_a dx_b
+  const double c = -0.5 * leb[4 * n + 3] * U[in];
+  const double ce = c * etag[in] * (eps1 / eps2);
+  for (int a = 0; a < 3; ++a) {
+    double hs = 0.0;
+    for (int b = 0; b < 3; ++b) hs += acc.g[a].g[b] * s[b];
+    fpt[3L * k + a] += c * xr[in] * acc.g[a].v + ce * hs;
+  }
+}
+
+// Laplace source terms by listed pairs (near part): the charge k moves, the points of the
+// listed spheres other than k do not.
+__global__ __launch_bounds__(256) void k_force_laplace_source_list(int N, const int* __restrict__ act_ptr,
+                                                                   const int* __restrict__ act_n,
+                                                                   const double* __restrict__ xyz,
+                                                                   const double* __restrict__ rad,
+                                                                   const double* __restrict__ leb,
+                                                                   const double* __restrict__ q, double eps1,
+                                                                   double eps2, const double* __restrict__ U,
+                                                                   const double* __restrict__ xr,
+                                                                   const double* __restrict__ etag,
+                                                                   const int* __restrict__ lptr,
+                                                                   const int* __restrict__ lidx,
+                                                                   double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int kq = blockIdx.x;
+  const double xk = xyz[3 * kq], yk = xyz[3 * kq + 1], zk = xyz[3 * kq + 2], qk = q[kq];
+  double acc[3] = {0, 0, 0};
+  for (int t = lptr[kq]; t < lptr[kq + 1]; ++t) {
+    const int i = lidx[t];
+    if (i == kq) continue;
+    for (int kk = act_ptr[i] + threadIdx.x; kk < act_ptr[i + 1]; kk += blockDim.x) {
+      const int n = act_n[kk];
+      const long in = (long)i * N + n;
+      const double c = -0.5 * leb[4 * n + 3] * U[in];
+      const double a1 = c * xr[in] / eps1, a2 = c * etag[in] / eps2;
+      const double s[3] = {leb[4 * n], leb[4 * n + 1], leb[4 * n + 2]};
+      const double v3[3] = {xyz[3 * i] + rad[i] * s[0] - xk, xyz[3 * i + 1] + rad[i] * s[1] - yk,
+                            xyz[3 * i + 2] + rad[i] * s[2] - zk};
+      const double d2 = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2], id = 1.0 / sqrt(d2), id2 = id * id,
+                   id3 = id2 * id;
+      const double vs = v3[0] * s[0] + v3[1] * s[1] + v3[2] * s[2];
+      for (int a = 0; a < 3; ++a) acc[a] -= qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3));
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    double s = block_sum(acc[c], sh);
+    if (threadIdx.x == 0) out[3L * kq + c] += s;
+  }
+}
+
+// Laplace target terms by listed pairs (near part), charges k != i of the listed spheres
+__global__ __launch_bounds__(256) void k_force_points_lap_list(int N, int nact, const int* __restrict__ act_sph,
+                                                               const int* __restrict__ act_n,
+                                                               const double* __restrict__ xyz,
+                                                               const double* __restrict__ rad,
+                                                               const double* __restrict__ leb,
+                                                               const double* __restrict__ q, double eps1, double eps2,
+                                                               const double* __restrict__ U,
+                                                               const double* __restrict__ xr,
+                                                               const double* __restrict__ etag,
+                                                               const int* __restrict__ lptr,
+                                                               const int* __restrict__ lidx,
+                                                               double* __restrict__ fpt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  const long in = (long)i * N + n;
+  double p[3], s[3];
+  for (int a = 0; a < 3; ++a) { s[a] = leb[4 * n + a]; p[a] = xyz[3 * i + a] + rad[i] * s[a]; }
+  const double c = -0.5 * leb[4 * n + 3] * U[in];
+  const double a1 = c * xr[in] / eps1, a2 = c * etag[in] / eps2;
+  double acc[3] = {0, 0, 0};
+  for (int t = lptr[i]; t < lptr[i + 1]; ++t) {
+    const int j = lidx[t];
+    if (j == i) continue;
+    const double vx = p[0] - xyz[3 * j], vy = p[1] - xyz[3 * j + 1], vz = p[2] - xyz[3 * j + 2];
+    const double d2 = vx * vx + vy * vy + vz * vz, id = 1.0 / sqrt(d2), id2 = id * id, id3 = id2 * id;
+    const double qk = q[j];
+    const double vs = vx * s[0] + vy * s[1] + vz * s[2];
+    const double v3[3] = {vx, vy, vz};
+    for (int a = 0; a < 3; ++a) acc[a] += qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3));
+  }
+  for (int a = 0; a < 3; ++a) fpt[3L * k + a] += acc[a];
+}
+
+// grids of the source-side Laplace functional: g1 = c xi_r / eps1, g2 = c eta / eps2, c = -1/2 w U
+__global__ void k_lap_src_grids(int M, int N, const double* __restrict__ leb, const double* __restrict__ U,
+                                const double* __restrict__ xr, const double* __restrict__ etag, double eps1,
+                                double eps2, double* __restrict__ g1, double* __restrict__ g2) {
+  const long g = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (g >= (long)M * N) return;
+  const int n = (int)(g % N);
+  const double c = -0.5 * leb[4 * n + 3] * U[g];
+  g1[g] = c * xr[g] / eps1;
+  g2[g] = c * etag[g] / eps2;
+}
+
+// Far Laplace source terms from the adjoint multipoles at the charges (degree >= 1):
+// grad_{x_k} += q_k sqrt(4 pi/3)/r_k^2 (Mu_k[1,1], Mu_k[1,-1], Mu_k[1,0])
+__global__ void k_force_lap_far_source(int M, int ldm, const double* __restrict__ q, const double* __restrict__ rad,
+                                       const double* __restrict__ Mu, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const double f = q[k] * 2.0466534158929770 / (rad[k] * rad[k]);  // sqrt(4 pi / 3)
+  out[3L * k + 0] += f * Mu[(long)k * ldm + 3];
+  out[3L * k + 1] += f * Mu[(long)k * ldm + 1];
+  out[3L * k + 2] += f * Mu[(long)k * ldm + 2];
+}
+
+}  // namespace ddlpb

@@ -1,0 +1,226 @@
+// Host side of the fast multipole method (Appendix): tree, interaction lists
+// and translation coefficient tables.
+//
+// Tree: binary, built by recursive median splits of the sphere centres along the
+// widest axis; every leaf is one sphere (so a leaf expansion is the sphere's own
+// expansion, centred at x_j with scale r_j).  Node radius R encloses every grid
+// point of the node's spheres (max |x_j - c| + r_j).
+// Lists: dual traversal with the acceptance test R_T + R_S < theta |c_T - c_S|;
+// accepted pairs are multipole-to-local translations, rejected leaf pairs are
+// evaluated directly (near list, sphere pairs).
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <numeric>
+#include <vector>
+
+#include "host_math.hpp"
+
+namespace ddlpb {
+namespace fmm {
+
+struct Tree {
+  int nnodes = 0, nlevels = 0;
+  std::vector<double> center;     // [nnodes][3]
+  std::vector<double> radius;     // [nnodes]
+  std::vector<int> child;         // [nnodes][2], -1 for leaves
+  std::vector<int> parent;        // [nnodes]
+  std::vector<int> level;         // [nnodes]
+  std::vector<int> leaf_sphere;   // [nnodes], sphere index of a leaf or -1
+  std::vector<int> sphere_leaf;   // [M], node index of the sphere's leaf
+  std::vector<int> level_ptr, level_nodes;  // nodes grouped by level (CSR)
+  // interaction lists
+  std::vector<int> m2l_ptr, m2l_src;  // per target node, source nodes (sorted)
+  std::vector<int> m2lt_ptr, m2lt_tgt;  // transposed: per source node, target nodes
+  std::vector<int> near_ptr, near_idx;  // per target sphere, source spheres (self included)
+};
+
+inline void build_tree(int M, const double* x, const double* r, Tree& t) {
+  std::vector<int> idx(M);
+  std::iota(idx.begin(), idx.end(), 0);
+  t.center.clear(); t.radius.clear(); t.child.clear(); t.parent.clear(); t.level.clear(); t.leaf_sphere.clear();
+  t.sphere_leaf.assign(M, -1);
+  std::function<int(int, int, int, int)> rec = [&](int lo, int hi, int par, int lev) -> int {
+    const int id = (int)t.radius.size();
+    t.center.resize(3 * (id + 1));
+    t.radius.push_back(0.0);
+    t.child.push_back(-1); t.child.push_back(-1);
+    t.parent.push_back(par);
+    t.level.push_back(lev);
+    t.leaf_sphere.push_back(-1);
+    double bmin[3] = {1e300, 1e300, 1e300}, bmax[3] = {-1e300, -1e300, -1e300};
+    for (int k = lo; k < hi; ++k)
+      for (int a = 0; a < 3; ++a) {
+        bmin[a] = std::min(bmin[a], x[3 * idx[k] + a]);
+        bmax[a] = std::max(bmax[a], x[3 * idx[k] + a]);
+      }
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (bmin[a] + bmax[a]);
+    if (hi - lo == 1) for (int a = 0; a < 3; ++a) c[a] = x[3 * idx[lo] + a];
+    double R = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      const int j = idx[k];
+      double d2 = 0;
+      for (int a = 0; a < 3; ++a) { double v = x[3 * j + a] - c[a]; d2 += v * v; }
+      R = std::max(R, std::sqrt(d2) + r[j]);
+    }
+    for (int a = 0; a < 3; ++a) t.center[3 * id + a] = c[a];
+    t.radius[id] = R;
+    if (hi - lo == 1) {
+      t.leaf_sphere[id] = idx[lo];
+      t.sphere_leaf[idx[lo]] = id;
+      return id;
+    }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a) if (bmax[a] - bmin[a] > bmax[ax] - bmin[ax]) ax = a;
+    const int mid = (lo + hi) / 2;
+    std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [&](int p, int q) {
+      if (x[3 * p + ax] != x[3 * q + ax]) return x[3 * p + ax] < x[3 * q + ax];
+      return p < q;
+    });
+    const int c0 = rec(lo, mid, id, lev + 1);
+    const int c1 = rec(mid, hi, id, lev + 1);
+    t.child[2 * id] = c0;
+    t.child[2 * id + 1] = c1;
+    return id;
+  };
+  rec(0, M, -1, 0);
+  t.nnodes = (int)t.radius.size();
+  t.nlevels = *std::max_element(t.level.begin(), t.level.end()) + 1;
+  t.level_ptr.assign(t.nlevels + 1, 0);
+  for (int v : t.level) t.level_ptr[v + 1]++;
+  for (int l = 0; l < t.nlevels; ++l) t.level_ptr[l + 1] += t.level_ptr[l];
+  t.level_nodes.assign(t.nnodes, 0);
+  std::vector<int> fillp(t.level_ptr.begin(), t.level_ptr.end() - 1);
+  for (int n = 0; n < t.nnodes; ++n) t.level_nodes[fillp[t.level[n]]++] = n;
+}
+
+inline void build_lists(int M, const double* r, double theta, Tree& t) {
+  std::vector<std::vector<int>> m2l(t.nnodes);
+  std::vector<std::vector<int>> near(M);
+  auto is_leaf = [&](int n) { return t.child[2 * n] < 0; };
+  std::function<void(int, int)> interact = [&](int T, int S) {
+    double d2 = 0;
+    for (int a = 0; a < 3; ++a) { double v = t.center[3 * T + a] - t.center[3 * S + a]; d2 += v * v; }
+    const double d = std::sqrt(d2);
+    if (T != S && t.radius[T] + t.radius[S] < theta * d) {
+      m2l[T].push_back(S);
+      return;
+    }
+    const bool lt = is_leaf(T), ls = is_leaf(S);
+    if (lt && ls) {
+      near[t.leaf_sphere[T]].push_back(t.leaf_sphere[S]);
+      return;
+    }
+    if (ls || (!lt && t.radius[T] >= t.radius[S])) {
+      interact(t.child[2 * T], S);
+      interact(t.child[2 * T + 1], S);
+    } else {
+      interact(T, t.child[2 * S]);
+      interact(T, t.child[2 * S + 1]);
+    }
+  };
+  interact(0, 0);
+  t.m2l_ptr.assign(t.nnodes + 1, 0);
+  t.m2l_src.clear();
+  std::vector<std::vector<int>> m2lt(t.nnodes);
+  for (int n = 0; n < t.nnodes; ++n) {
+    std::sort(m2l[n].begin(), m2l[n].end());
+    t.m2l_src.insert(t.m2l_src.end(), m2l[n].begin(), m2l[n].end());
+    t.m2l_ptr[n + 1] = (int)t.m2l_src.size();
+    for (int s : m2l[n]) m2lt[s].push_back(n);
+  }
+  t.m2lt_ptr.assign(t.nnodes + 1, 0);
+  t.m2lt_tgt.clear();
+  for (int n = 0; n < t.nnodes; ++n) {
+    std::sort(m2lt[n].begin(), m2lt[n].end());
+    t.m2lt_tgt.insert(t.m2lt_tgt.end(), m2lt[n].begin(), m2lt[n].end());
+    t.m2lt_ptr[n + 1] = (int)t.m2lt_tgt.size();
+  }
+  t.near_ptr.assign(M + 1, 0);
+  t.near_idx.clear();
+  for (int i = 0; i < M; ++i) {
+    std::sort(near[i].begin(), near[i].end());
+    t.near_idx.insert(t.near_idx.end(), near[i].begin(), near[i].end());
+    t.near_ptr[i + 1] = (int)t.near_idx.size();
+  }
+  (void)r;
+}
+
+// ------------------------------------------------------ coefficient tables
+inline double lfact(int n) { return std::lgamma(n + 1.0); }
+inline double dfact(int n) { double v = 1.0; for (int k = n; k > 1; k -= 2) v *= k; return v; }
+// normalisation of the real harmonics with the sign (-1)^m for m != 0
+inline double ntil(int l, int m) {
+  const int am = std::abs(m);
+  if (am == 0) return std::sqrt((2.0 * l + 1.0) / (4.0 * host::kPi));
+  const double s = (am % 2) ? -1.0 : 1.0;
+  return s * std::sqrt(2.0 * (2.0 * l + 1.0) / (4.0 * host::kPi) * std::exp(lfact(l - am) - lfact(l + am)));
+}
+// C_N(l, m, l') = N(l,m) (2l'+1) (l'-|m|)! (l+|m|)! / N(l',m)
+inline double cn(int l, int m, int lp) {
+  const int am = std::abs(m);
+  return ntil(l, m) / ntil(lp, m) * (2.0 * lp + 1.0) * std::exp(lfact(lp - am) + lfact(l + am));
+}
+// C_{l m k}^{l'} = (2k)! / (2^k (k+m)! k! (k-m)! (l'-k)! (l-k)!)
+inline double clmk(int l, int m, int k, int lp) {
+  return std::exp(lfact(2 * k) - k * std::log(2.0) - lfact(k + m) - lfact(k) - lfact(k - m) - lfact(lp - k) - lfact(l - k));
+}
+
+struct Tables {
+  int pmax = 0;
+  // Yukawa: A[((l*(P1) + l')*(P1) + |m|)*(P1) + k] = C_N C_{lmk}^{l'}
+  std::vector<double> A;
+  // Laplace: per kind (0 m2m, 1 m2l, 2 l2l): AL[kind][(l*(P1) + l')*(P1) + |m|]
+  std::vector<double> AL;
+  // rotation by +90 degrees about x: packed blocks J_l [(2l+1)^2], row m'+l, column m+l
+  std::vector<double> J;
+  std::vector<int> Joff;
+};
+
+inline void build_tables(int pmax, Tables& tb) {
+  const int P1 = pmax + 1;
+  tb.pmax = pmax;
+  tb.A.assign((size_t)P1 * P1 * P1 * P1, 0.0);
+  tb.AL.assign((size_t)3 * P1 * P1 * P1, 0.0);
+  for (int l = 0; l <= pmax; ++l)
+    for (int lp = 0; lp <= pmax; ++lp)
+      for (int am = 0; am <= std::min(l, lp); ++am) {
+        const double c = cn(l, am, lp);
+        for (int k = am; k <= std::min(l, lp); ++k)
+          tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k] = c * clmk(l, am, k, lp);
+        // Laplace limits of the scaled Yukawa translations
+        const size_t o = ((size_t)l * P1 + lp) * P1 + am;
+        if (lp >= l)  // M2M keeps k = l
+          tb.AL[0 * (size_t)P1 * P1 * P1 + o] = c * clmk(l, am, l, lp) * dfact(2 * lp - 1) / (dfact(2 * l - 1) * dfact(2 * lp + 1));
+        double s = 0.0;  // M2L keeps every k
+        for (int k = am; k <= std::min(l, lp); ++k)
+          s += clmk(l, am, k, lp) * dfact(2 * l + 2 * lp - 2 * k - 1) * ((k % 2) ? -1.0 : 1.0);
+        tb.AL[1 * (size_t)P1 * P1 * P1 + o] = c * ((l % 2) ? -1.0 : 1.0) * s / (dfact(2 * lp + 1) * dfact(2 * l - 1));
+        if (l >= lp)  // L2L keeps k = l'
+          tb.AL[2 * (size_t)P1 * P1 * P1 + o] = c * clmk(l, am, lp, lp) * (((l + lp) % 2) ? -1.0 : 1.0) * dfact(2 * l + 1) /
+                                                 (dfact(2 * lp + 1) * dfact(2 * l + 1));
+      }
+  // J_l[m', m] = sum_n w_n Y_lm'(s_n) Y_lm(Q^T s_n), Q = rotation by +90 degrees about x,
+  // exact for a Lebedev rule of degree >= 2 pmax.
+  const auto* rule = host::lebedev_rule_min_degree(2 * pmax);
+  const int L = P1 * P1;
+  tb.Joff.assign(P1 + 1, 0);
+  for (int l = 0; l <= pmax; ++l) tb.Joff[l + 1] = tb.Joff[l] + (2 * l + 1) * (2 * l + 1);
+  tb.J.assign(tb.Joff[P1], 0.0);
+  std::vector<double> Y(L), YQ(L);
+  for (int n = 0; n < rule->n; ++n) {
+    const double* s = rule->xyzw + 4 * n;
+    host::solid_harmonics<double>(pmax, s[0], s[1], s[2], Y.data());
+    // Q^T s for Q = Rx(90): Q = [[1,0,0],[0,0,-1],[0,1,0]], Q^T s = (s_x, s_z, -s_y)
+    host::solid_harmonics<double>(pmax, s[0], s[2], -s[1], YQ.data());
+    for (int l = 0; l <= pmax; ++l)
+      for (int a = -l; a <= l; ++a)
+        for (int b = -l; b <= l; ++b)
+          tb.J[tb.Joff[l] + (a + l) * (2 * l + 1) + (b + l)] += s[3] * Y[host::lmi(l, a)] * YQ[host::lmi(l, b)];
+  }
+}
+
+}  // namespace fmm
+}  // namespace ddlpb

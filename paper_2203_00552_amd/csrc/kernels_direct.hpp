@@ -66,6 +66,25 @@ __global__ void k_active_fill(int M, int N, const double* __restrict__ U, const 
     if (U[(long)i * N + n] > 0.0) { act_sph[k] = i; act_n[k] = n; ++k; }
 }
 
+// cap pairs (i, n, j) with |x_i^n - x_j| < r_j, i.e. omega_ij(x_i^n) > 0, per sphere
+__global__ void k_cap_count(int M, int N, const double* __restrict__ xyz, const double* __restrict__ rad,
+                            const double* __restrict__ leb, const int* __restrict__ nptr,
+                            const int* __restrict__ nidx, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int c = 0;
+  for (int n = 0; n < N; ++n) {
+    const double px = xyz[3 * i] + rad[i] * leb[4 * n], py = xyz[3 * i + 1] + rad[i] * leb[4 * n + 1],
+                 pz = xyz[3 * i + 2] + rad[i] * leb[4 * n + 2];
+    for (int a = nptr[i]; a < nptr[i + 1]; ++a) {
+      const int j = nidx[a];
+      const double dx = px - xyz[3 * j], dy = py - xyz[3 * j + 1], dz = pz - xyz[3 * j + 2];
+      c += (dx * dx + dy * dy + dz * dz < rad[j] * rad[j]);
+    }
+  }
+  cnt[i] = c;
+}
+
 __global__ void k_fill(long n, double v, double* __restrict__ a) {
   long g = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (g < n) a[g] = v;
@@ -229,6 +248,106 @@ __global__ __launch_bounds__(256) void k_sl_adjoint_direct(int M, int N, int nac
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * LO + t];
     lam[(long)j * LO + t] = s;
+  }
+}
+
+// ------------------------------------------- single-layer field (listed pairs)
+// Same field as k_sl_field_direct, restricted to the source spheres listed for the
+// target point's own sphere (CSR lptr/lidx): the near part of a split evaluation.
+template <int LM, bool GRAD>
+__global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, const int* __restrict__ act_sph,
+                                                        const int* __restrict__ act_n, const double* __restrict__ xyz,
+                                                        const double* __restrict__ rad, const double* __restrict__ leb,
+                                                        const int* __restrict__ lptr, const int* __restrict__ lidx,
+                                                        const double* __restrict__ m, const double* __restrict__ ur,
+                                                        int LUR, double kappa, int exclude_self, int accumulate,
+                                                        double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  double p[3];
+  for (int a = 0; a < 3; ++a) p[a] = xyz[3 * i + a] + rad[i] * leb[4 * n + a];
+  using T = typename std::conditional<GRAD, Dual<double>, double>::type;
+  T acc(0.0);
+  for (int q = lptr[i]; q < lptr[i + 1]; ++q) {
+    const int j = lidx[q];
+    if (exclude_self && j == i) continue;
+    const double rj = rad[j], irj = 1.0 / rj;
+    T v[3];
+    for (int a = 0; a < 3; ++a) {
+      v[a] = T(p[a]);
+      if constexpr (GRAD) v[a].g[a] = 1.0;
+      v[a] = (v[a] - T(xyz[3 * j + a])) * irj;
+    }
+    T rho = dsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * rj;
+    T u[LM + 1];
+    k_weights<LM, T>(rho, kappa, u);
+    const double* mc = m + (long)j * L;
+    T part[LM + 1];
+#pragma unroll
+    for (int l = 0; l <= LM; ++l) part[l] = T(0.0);
+    for_each_solid_harmonic<LM, T>(v[0], v[1], v[2], [&](int l, int idx, const T& S) { part[l] = part[l] + mc[idx] * S; });
+#pragma unroll
+    for (int l = 0; l <= LM; ++l) acc = acc + (u[l] * (1.0 / ur[j * LUR + l])) * part[l];
+  }
+  if constexpr (GRAD) {
+    for (int a = 0; a < 3; ++a) out[3L * k + a] = (accumulate ? out[3L * k + a] : 0.0) + acc.g[a];
+  } else {
+    const long in = (long)i * N + n;
+    out[in] = (accumulate ? out[in] : 0.0) + acc;
+  }
+}
+
+// Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
+// for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
+template <int LMO>
+__global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
+                                                          const int* __restrict__ act_n, const double* __restrict__ xyz,
+                                                          const double* __restrict__ rad, const double* __restrict__ leb,
+                                                          const int* __restrict__ lptr, const int* __restrict__ lidx,
+                                                          const double* __restrict__ cgrid, const double* __restrict__ ur,
+                                                          int LUR, double kappa, int exclude_self, int accumulate,
+                                                          int LDL, double* __restrict__ lam) {
+  constexpr int LO = (LMO + 1) * (LMO + 1);
+  __shared__ double red[4 * LO];
+  const int j = blockIdx.x;
+  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
+  double iu[LMO + 1];
+#pragma unroll
+  for (int l = 0; l <= LMO; ++l) iu[l] = 1.0 / ur[j * LUR + l];
+  double acc[LO];
+#pragma unroll
+  for (int t = 0; t < LO; ++t) acc[t] = 0.0;
+  for (int q = lptr[j]; q < lptr[j + 1]; ++q) {
+    const int i = lidx[q];
+    if (exclude_self && i == j) continue;
+    for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x) {
+      const int n = act_n[k];
+      const double c = cgrid[(long)i * N + n];
+      if (c == 0.0) continue;
+      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
+      double u[LMO + 1];
+      k_weights<LMO, double>(rho, kappa, u);
+#pragma unroll
+      for (int l = 0; l <= LMO; ++l) u[l] *= c * iu[l];
+      for_each_solid_harmonic<LMO, double>(vx, vy, vz, [&](int l, int idx, double S) { acc[idx] += u[l] * S; });
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < LO; ++t) {
+    double v = wave_sum(acc[t]);
+    if (lane == 0) red[wid * LO + t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < LO; t += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * LO + t];
+    lam[(long)j * LDL + t] = (accumulate ? lam[(long)j * LDL + t] : 0.0) + s;
   }
 }
 

@@ -1,0 +1,87 @@
+"""Fast multipole path against the direct path and the oracle (GPU, through the C ABI).
+
+The FMM only approximates the direct sums, so it is not expected to reproduce the
+oracle to 1e-8; the bars here are the measured truncation errors at the tested
+orders (relative to the largest entry), the exactness of the adjoint (the
+transposed FMM is the exact transpose of the forward FMM), and monotone decrease
+of the error with the order p."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_00552_amd import Context, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def cluster():
+    return inputs.lattice_cluster(300, seed=4)
+
+
+def test_fmm_operator_matches_direct(cluster):
+    x, r, q = cluster
+    d = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=0)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(2, len(r), 49)) * np.exp(-0.4 * np.repeat(np.arange(7), 2 * np.arange(7) + 1))
+    Yd = d.apply(X)
+    YdT = d.apply(X, transpose=True)
+    errs = []
+    for p in (8, 12):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=p)
+        errs.append((_rel(f.apply(X), Yd), _rel(f.apply(X, transpose=True), YdT)))
+    assert errs[-1][0] < 1e-6 and errs[-1][1] < 1e-6, errs
+    assert errs[-1][0] < errs[0][0] and errs[-1][1] < errs[0][1], errs
+
+
+def test_fmm_adjoint_is_exact_transpose(cluster):
+    x, r, q = cluster
+    f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=10)
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(2, len(r), 49))
+    Z = rng.normal(size=(2, len(r), 49))
+    a = (f.apply(X) * Z).sum()
+    b = (X * f.apply(Z, transpose=True)).sum()
+    assert abs(a - b) < 1e-11 * abs(a)
+
+
+def test_fmm_rhs_matches_direct(cluster):
+    x, r, q = cluster
+    d = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=0)
+    f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=12)
+    assert _rel(f.rhs(), d.rhs()) < 1e-6
+
+
+def test_fmm_energy_forces_vs_oracle():
+    """Energy and forces with FMM p = 12 against the oracle (direct sums) on a 120-atom
+    cluster: the FMM truncation error stays far below the discretisation error."""
+    x, r, q = inputs.lattice_cluster(120, seed=5)
+    ref = oracle.Problem(x, r, q, lmax=6, n_lebedev=302).solve("gmres", tol=1e-11)
+    out = {}
+    for p in (8, 12):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=p)
+        E = f.solve(1e-11)
+        f.adjoint(1e-11)
+        F = f.forces()
+        out[p] = (abs(E / ref["energy"] - 1), _rel(F, ref["forces"]))
+    assert out[12][0] < 1e-7 and out[12][1] < 1e-5, out
+    assert out[12][0] <= out[8][0] * 1.01 and out[12][1] <= out[8][1] * 1.01, out
+
+
+def test_fmm_forces_match_direct_gpu():
+    """FMM forces against the GPU direct path at 400 atoms, lmax 8 (p = 12)."""
+    x, r, q = inputs.lattice_cluster(400, seed=6)
+    d = Context(x, r, q, lmax=8, n_lebedev=302, fmm_order=0)
+    Ed = d.solve(1e-10)
+    d.adjoint(1e-10)
+    Fd = d.forces()
+    f = Context(x, r, q, lmax=8, n_lebedev=302, fmm_order=12)
+    Ef = f.solve(1e-10)
+    f.adjoint(1e-10)
+    Ff = f.forces()
+    assert abs(Ef / Ed - 1) < 1e-6
+    assert _rel(Ff, Fd) < 1e-4

@@ -38,7 +38,9 @@ def test_intermediates_config1():
     ctx, P = _pair(x, r, q, 6, 110)
     f, U = ctx.grid()
     fo, Uo, _ = P.grid_fields()
-    assert np.abs(f - fo).max() < 1e-13 and np.abs(U - Uo).max() < 1e-13
+    # the oracle evaluates the paper's polynomial form of p_eta (with eta^-5), the kernel the
+    # equal smoothstep form in u = (1-t)/eta: rounding differs by O(1e-16/eta)
+    assert np.abs(f - fo).max() < 1e-12 and np.abs(U - Uo).max() < 1e-12
     g = ctx.rhs()
     go = P.rhs()
     assert np.abs(g - go).max() < 1e-12 * np.abs(go).max()
