@@ -68,10 +68,13 @@ struct ddlpb_ctx {
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
   double theta = 0.5;
+  int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic)
   // ---- host analysis
   std::vector<int> nptr, nidx, nrev;
   std::vector<int> pptr, pidx;  // sphere pairs of the near preconditioner (self included)
   size_t nnz_cap = 0, pnz_cap = 0;  // capacities of the device copies of nidx / pidx
+  size_t cap_est = 0, cap_cap = 0;  // estimated cap pairs and the capacity of the cap lists
+  bool use_caps = false;            // cap lists built for the current geometry
   int nterms = 8, nterms_p = 8;
   // ---- device
   hipStream_t stream = nullptr;
@@ -92,6 +95,9 @@ struct ddlpb_ctx {
          *d_t2 = nullptr, *d_t3 = nullptr, *d_V = nullptr;
   double *d_part = nullptr, *d_hv = nullptr, *d_scal = nullptr;
   int *d_pptr = nullptr, *d_pidx = nullptr;
+  int *d_cptr = nullptr, *d_capn = nullptr, *d_capslot = nullptr, *d_pcp = nullptr, *d_rptr = nullptr,
+      *d_rci = nullptr, *d_rcn = nullptr;
+  double *d_capw = nullptr, *d_rcw = nullptr;
   double *d_Z = nullptr, *d_Vin = nullptr, *d_t4 = nullptr, *d_t5 = nullptr;
   double *d_fnb = nullptr, *d_fself = nullptr, *d_fpt = nullptr, *d_fpts = nullptr, *d_flsrc = nullptr,
          *d_fysrc = nullptr, *d_gphi = nullptr, *d_F = nullptr;
@@ -106,7 +112,9 @@ struct ddlpb_ctx {
   double *d_fcen = nullptr, *d_frad = nullptr, *d_fkR = nullptr, *d_fiR = nullptr, *d_fA = nullptr, *d_fAL = nullptr,
          *d_fJ = nullptr, *d_Mn = nullptr, *d_Ln = nullptr, *d_SL = nullptr, *d_Lam = nullptr, *d_sgp = nullptr,
          *d_qsrc = nullptr, *d_tmp4 = nullptr;
-  int *d_fJoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
+  double* d_fjval = nullptr;
+  int* d_fjrow = nullptr;
+  int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
       *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
       *d_sleaf = nullptr;
   double near_pts_fmm = 0.0;  // (active point, near source sphere) pairs of the FMM near list
@@ -186,6 +194,19 @@ int build_neighbours(ddlpb_ctx* c) {
   }
   c->nptr.assign(M + 1, 0);
   for (int i = 0; i < M; ++i) c->nptr[i + 1] = c->nptr[i] + (int)nb[i].size();
+  // cap pairs: the fraction of sphere i's surface inside ball j is (1 - c0)/2 with
+  // c0 = (r_i^2 + d^2 - r_j^2) / (2 r_i d); Lebedev points are close to uniform.
+  double est = 0.0;
+  for (int i = 0; i < M; ++i)
+    for (int j : nb[i]) {
+      double d2 = 0;
+      for (int a = 0; a < 3; ++a) { double t = c->x[3 * i + a] - c->x[3 * j + a]; d2 += t * t; }
+      const double d = std::sqrt(d2);
+      double c0 = (c->r[i] * c->r[i] + d2 - c->r[j] * c->r[j]) / (2.0 * c->r[i] * d);
+      c0 = std::min(1.0, std::max(-1.0, c0));
+      est += std::ceil(1.25 * c->N * 0.5 * (1.0 - c0) + 8.0);
+    }
+  c->cap_est = (size_t)est;
   c->nidx.resize(c->nptr[M]);
   c->nrev.resize(c->nptr[M]);
   for (int i = 0; i < M; ++i) std::copy(nb[i].begin(), nb[i].end(), c->nidx.begin() + c->nptr[i]);
@@ -304,6 +325,16 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_t4 = cv.take<double>(D);
   c->d_t5 = cv.take<double>(D);
   c->d_pptr = cv.take<int>(M + 1);
+  c->cap_cap = std::max(c->cap_cap, c->cap_est);
+  c->d_cptr = cv.take<int>(M + 1);
+  c->d_rptr = cv.take<int>(M + 1);
+  c->d_pcp = cv.take<int>(M * (N + 1));
+  c->d_capn = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
+  c->d_capslot = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
+  c->d_capw = cv.take<double>(std::max<size_t>(c->cap_cap, 1));
+  c->d_rci = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
+  c->d_rcn = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
+  c->d_rcw = cv.take<double>(std::max<size_t>(c->cap_cap, 1));
   c->d_pidx = cv.take<int>(std::max<size_t>(c->pnz_cap, 1));
   const int mk = std::max(c->restart, c->inner_iters) + 2;
   c->d_part = cv.take<double>((size_t)mk * c->nb_dot);
@@ -335,10 +366,13 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
     c->d_fm2ltt = cv.take<int>(std::max<size_t>(c->m2l_cap, 1));
     c->d_fnp = cv.take<int>(M + 1);
     c->d_fni = cv.take<int>(std::max<size_t>(c->near_cap, 1));
-    c->d_fA = cv.take<double>(p1 * p1 * p1 * p1);
+    c->d_fA = cv.take<double>(std::max<size_t>(c->tables.Ap.size(), 1));
+    c->d_fAoff = cv.take<int>(p1 * p1 * p1);
     c->d_fAL = cv.take<double>(3 * p1 * p1 * p1);
     c->d_fJ = cv.take<double>(std::max<size_t>(c->tables.J.size(), 1));
     c->d_fJoff = cv.take<int>(p1 + 1);
+    c->d_fjval = cv.take<double>(std::max<size_t>(c->tables.Jval.size(), 1));
+    c->d_fjrow = cv.take<int>(std::max<size_t>(c->tables.Jrow.size(), 1));
     c->d_Mn = cv.take<double>(nn * P);
     c->d_Ln = cv.take<double>(nn * P);
     c->d_SL = cv.take<double>(M * P);
@@ -487,6 +521,14 @@ void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, dou
 void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
               const double* gr2, const double* ge, double cg, double* out) {
   KScope ks(c, "apply_LX", nearX ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
+  if (c->use_caps) {
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LX_caps<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+                                            c->LY, c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx,
+                                            c->d_cptr, c->d_capn, c->d_capslot, c->d_capw, c->d_pcp, c->d_U, c->d_sgr,
+                                            c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1, gr2, ge, cg, out));
+    HIPCHK(hipGetLastError());
+    return;
+  }
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LX<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U,
                                           c->d_sgr, c->LUR, c->kappa, c->eta, c->nterms, base, c0, nearX, c1, gr1,
@@ -503,6 +545,14 @@ void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
 void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
                const double* lam, int llam, double* out) {
   KScope ks(c, "apply_LTZ", zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
+  if (c->use_caps) {
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LTZ_caps<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+                                            c->LY, c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci,
+                                            c->d_rcn, c->d_rcw, c->d_U, c->d_sgr, c->d_ycr, c->d_yce, c->d_Cl, c->LUR,
+                                            c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam, out));
+    HIPCHK(hipGetLastError());
+    return;
+  }
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LTZ<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U,
                                           c->d_sgr, c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->eta, c->nterms,
@@ -542,7 +592,9 @@ FmmDev fmm_dev(ddlpb_ctx* c, int kernel) {
   f.kernel = kernel;
   f.p = c->fmm_order;
   f.kappa = c->kappa;
-  f.A = c->d_fA; f.AL = c->d_fAL; f.J = c->d_fJ; f.Joff = c->d_fJoff;
+  f.A = c->d_fA; f.Aoff = c->d_fAoff; f.nA = (int)c->tables.Ap.size();
+  f.AL = c->d_fAL; f.J = c->d_fJ; f.Joff = c->d_fJoff;
+  f.jval = c->d_fjval; f.jrow = c->d_fjrow; f.njval = (int)c->tables.Jval.size();
   f.center = c->d_fcen; f.radius = c->d_frad; f.kR = c->d_fkR; f.iR = c->d_fiR;
   return f;
 }
@@ -555,12 +607,78 @@ inline double flops_translation(int p) {
       for (int m = -std::min(l, lp); m <= std::min(l, lp); ++m) oz += 2.0 * (std::min(l, lp) - std::abs(m) + 1) + 4.0;
   return 8.0 * rot + oz;
 }
+// flops of one multipole-to-local translation as k_fmm_m2l_fast performs it: four sparse
+// rotations by J, four z-rotations, the z translation per (l_out, |m|, l_in)
+inline double flops_m2l_fast(int kernel, int p, size_t njval) {
+  double oz = 0.0;
+  for (int lo = 0; lo <= p; ++lo)
+    for (int am = 0; am <= lo; ++am)
+      for (int li = am; li <= p; ++li) {
+        const int nk = std::min(lo, li) - am + 1;
+        oz += (kernel == 0 ? 3.0 * nk + 3.0 : 2.0) + (am ? 4.0 : 2.0);
+      }
+  return 2.0 * 2.0 * (double)njval + 4.0 * 6.0 * p * (p + 1) / 2.0 + oz;
+}
+// LDS configuration of k_fmm_m2l_fast: wavefronts per block and whether the
+// coefficient tables fit in LDS next to the rotation rows (0 waves: not usable)
+void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes) {
+  int dev = 0, maxlds = 0, cu_lds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  HIPCHK(hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+  cu_lds = std::max(cu_lds, maxlds);
+  const int p = c->fmm_order;
+  const int nA = (int)c->tables.Ap.size(), nj = (int)c->tables.Jval.size();
+  // most resident wavefronts per compute unit (at most 32); ties go to the tables in
+  // LDS, then to larger blocks
+  nw = 0;
+  alds = false;
+  bytes = 0;
+  int best = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool a = pass == 0;
+    for (int w : {16, 8, 4, 2, 1}) {
+      if (c->m2l_waves > 0 && w != c->m2l_waves) continue;
+      const size_t b = m2l_fast_lds_bytes(kernel, p, nA, nj, w, a);
+      if (b > (size_t)maxlds) continue;
+      const int blocks = std::min((int)((size_t)cu_lds / b), 32 / w);
+      const int waves = w * blocks;
+      if (waves > best) { best = waves; nw = w; alds = a; bytes = b; }
+    }
+  }
+}
+void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx, int transposed, const double* in,
+                double* out) {
+  const auto& t = c->tree;
+  KScope ks(c, f.kernel == 0 ? (transposed ? "m2l_yukawa_T" : "m2l_yukawa") : (transposed ? "m2l_laplace_T" : "m2l_laplace"),
+            flops_m2l_fast(f.kernel, f.p, c->tables.Jval.size()) * (double)t.m2l_src.size());
+  int nw;
+  bool alds;
+  size_t bytes;
+  m2l_config(c, f.kernel, nw, alds, bytes);
+  if (nw > 0) {
+    const void* fn = alds ? reinterpret_cast<const void*>(&k_fmm_m2l_fast<true>)
+                          : reinterpret_cast<const void*>(&k_fmm_m2l_fast<false>);
+    if (bytes > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    const int blocks = std::max(1, std::min((t.nnodes + nw - 1) / nw, 4096));
+    if (alds)
+      hipLaunchKernelGGL(k_fmm_m2l_fast<true>, dim3(blocks), dim3(64 * nw), bytes, c->stream, f, t.nnodes, lptr, lidx,
+                         transposed, in, out);
+    else
+      hipLaunchKernelGGL(k_fmm_m2l_fast<false>, dim3(blocks), dim3(64 * nw), bytes, c->stream, f, t.nnodes, lptr, lidx,
+                         transposed, in, out);
+  } else {
+    hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, lptr, lidx,
+                       transposed, in, out);
+  }
+  HIPCHK(hipGetLastError());
+}
 // sphere locals SL [M][P] of the far field of per-sphere sources src (degree ps, stride lds)
 void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, double* SL) {
   const auto& t = c->tree;
   const int p = c->fmm_order, P = (p + 1) * (p + 1);
   FmmDev f = fmm_dev(c, kernel);
-  KScope ks(c, kernel == 0 ? "fmm_yukawa" : "fmm_laplace",
+  KScope ks(c, kernel == 0 ? "pass_fmm_yukawa" : "pass_fmm_laplace",
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, ps, lds, c->d_sleaf, src, c->d_Mn);
   for (int lev = t.nlevels - 2; lev >= 0; --lev) {
@@ -568,8 +686,7 @@ void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, d
     hipLaunchKernelGGL(k_fmm_upward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
                        c->d_fchild, c->d_Mn);
   }
-  hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, c->d_fm2lp,
-                     c->d_fm2ls, 0, c->d_Mn, c->d_Ln);
+  launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 0, c->d_Mn, c->d_Ln);
   for (int lev = 1; lev < t.nlevels; ++lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
     hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
@@ -583,7 +700,7 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
   const auto& t = c->tree;
   const int p = c->fmm_order, P = (p + 1) * (p + 1);
   FmmDev f = fmm_dev(c, kernel);
-  KScope ks(c, kernel == 0 ? "fmm_yukawa_T" : "fmm_laplace_T",
+  KScope ks(c, kernel == 0 ? "pass_fmm_yukawa_T" : "pass_fmm_laplace_T",
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   fill(c, c->d_Ln, (long)t.nnodes * P, 0.0);
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, Lam, c->d_Ln);
@@ -592,8 +709,7 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
     hipLaunchKernelGGL(k_fmm_upward_T, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
                        c->d_fchild, c->d_Ln);
   }
-  hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, c->d_fm2ltp,
-                     c->d_fm2ltt, 1, c->d_Ln, c->d_Mn);
+  launch_m2l(c, f, c->d_fm2ltp, c->d_fm2ltt, 1, c->d_Ln, c->d_Mn);
   for (int lev = 1; lev < t.nlevels; ++lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
     hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
@@ -846,11 +962,13 @@ void upload_and_init(ddlpb_ctx* c) {
     }
   }
   c->nterms = host::sigma_terms(c->lmax, c->kappa * c->kappa * rmax * rmax);
-  // Y table up to degree lmax+1
+  // Y table up to degree max(lmax + 1, p): the local expansions of degree p are
+  // evaluated on the sphere grids in full
   std::vector<double> Y((size_t)N * c->LY);
+  const int ydeg = (int)std::lround(std::sqrt((double)c->LY)) - 1;
   for (int n = 0; n < N; ++n) {
     const double* s = c->rule->xyzw + 4 * n;
-    host::solid_harmonics<double>(c->lmax + 1, s[0], s[1], s[2], &Y[(size_t)n * c->LY]);
+    host::solid_harmonics<double>(ydeg, s[0], s[1], s[2], &Y[(size_t)n * c->LY]);
   }
   std::vector<double> dtab;
   host::gradient_coupling(c->lmax, dtab);
@@ -876,10 +994,13 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_dtab, dtab.data(), dtab.size() * sizeof(double));
   if (c->fmm_order > 0) {
     const int p1 = c->fmm_order + 1;
-    up(c->d_fA, c->tables.A.data(), c->tables.A.size() * sizeof(double));
+    up(c->d_fA, c->tables.Ap.data(), c->tables.Ap.size() * sizeof(double));
+    up(c->d_fAoff, c->tables.Aoff.data(), c->tables.Aoff.size() * sizeof(int));
     up(c->d_fAL, c->tables.AL.data(), c->tables.AL.size() * sizeof(double));
     up(c->d_fJ, c->tables.J.data(), c->tables.J.size() * sizeof(double));
     up(c->d_fJoff, c->tables.Joff.data(), c->tables.Joff.size() * sizeof(int));
+    up(c->d_fjval, c->tables.Jval.data(), c->tables.Jval.size() * sizeof(double));
+    up(c->d_fjrow, c->tables.Jrow.data(), c->tables.Jrow.size() * sizeof(int));
     // sigma_l(kappa^2 r_i^2) up to degree p (normalisation of the sphere locals)
     std::vector<double> sgp((size_t)M * (p1 + 1)), sgt(p1 + 2), qs(M);
     for (int j = 0; j < M; ++j) {
@@ -950,6 +1071,24 @@ void geometry_on_device(ddlpb_ctx* c) {
   c->ncap = 0;
   for (int i = 0; i < M; ++i) c->ncap += cnt[i];
   c->stats.n_cap_pairs = c->ncap;
+  c->use_caps = (size_t)c->ncap <= c->cap_cap;
+  if (c->use_caps) {
+    std::vector<int> cp(M + 1, 0);
+    for (int i = 0; i < M; ++i) cp[i + 1] = cp[i] + cnt[i];
+    HIPCHK(hipMemcpyAsync(c->d_cptr, cp.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_caps_fill, dim3(nblk(M, 64)), dim3(64), 0, c->stream, M, N, c->d_xyz, c->d_rad, c->d_leb,
+                       c->d_nptr, c->d_nidx, c->d_f, c->eta, c->d_cptr, c->d_capn, c->d_capslot, c->d_capw, c->d_pcp);
+    hipLaunchKernelGGL(k_rcaps_count, dim3(nblk(M, 64)), dim3(64), 0, c->stream, M, N, c->d_xyz, c->d_rad, c->d_leb,
+                       c->d_nptr, c->d_nidx, c->d_actcnt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cnt.data(), c->d_actcnt, M * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < M; ++i) cp[i + 1] = cp[i] + cnt[i];
+    HIPCHK(hipMemcpyAsync(c->d_rptr, cp.data(), (M + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_rcaps_fill, dim3(nblk(M, 64)), dim3(64), 0, c->stream, M, N, c->d_xyz, c->d_rad, c->d_leb,
+                       c->d_nptr, c->d_nidx, c->d_f, c->eta, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw);
+    HIPCHK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_active_fill, dim3(nblk(M, 128)), dim3(128), 0, c->stream, M, N, c->d_U, c->d_actptr,
                      c->d_actsph, c->d_actn);
   HIPCHK(hipGetLastError());
@@ -1056,6 +1195,8 @@ int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, con
       fmm::build_tables(fmm_order, c->tables);
       fmm::build_tree(c->M, c->x.data(), c->r.data(), c->tree);
       fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+      c->stats.n_m2l = (int64_t)c->tree.m2l_src.size();
+      c->stats.n_near_pairs = (int64_t)c->tree.near_idx.size();
     }
     c->stats.fmm_order = fmm_order;
     c->stats.fmm_order_below_lmax = (fmm_order > 0 && fmm_order < lmax) ? 1 : 0;
@@ -1261,10 +1402,18 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 1 && v <= 4096)) return DDLPB_EINVAL;
     c->leaf = (int)v;
+  } else if (k == "m2l_waves") {
+    if (!(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
+    c->m2l_waves = (int)v;
   } else if (k == "theta") {
     if (fixed) return DDLPB_ESTATE;
     if (!(v > 0 && v < 1)) return DDLPB_EINVAL;
     c->theta = v;
+    if (c->fmm_order > 0) {
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+      c->stats.n_m2l = (int64_t)c->tree.m2l_src.size();
+      c->stats.n_near_pairs = (int64_t)c->tree.near_idx.size();
+    }
   } else {
     return DDLPB_EINVAL;
   }
@@ -1283,7 +1432,7 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
     if (rc) { c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; return rc; }
     build_pairs(c, c->pdelta, c->pptr, c->pidx);
     if (c->dev_ready) {
-      const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap;
+      const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap || c->cap_est > c->cap_cap;
       if (relayout) {
         // list capacities exceeded: the workspace layout changes; keep X and X_adj
         std::vector<double> X(2L * c->M * c->L), Xa(2L * c->M * c->L);
@@ -1292,6 +1441,7 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
         HIPCHK(hipStreamSynchronize(c->stream));
         c->nnz_cap = c->nidx.size() + c->nidx.size() / 4 + 64;
         c->pnz_cap = c->pidx.size() + c->pidx.size() / 4 + 64;
+        c->cap_cap = c->cap_est + c->cap_est / 4 + 64;
         size_t need = workspace_size(c);
         if (c->ws_bound && need > c->ws_bytes) return DDLPB_ENOMEM;
         if (c->ws_owned && need > c->ws_bytes) {

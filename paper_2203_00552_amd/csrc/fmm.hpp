@@ -25,10 +25,15 @@ struct FmmDev {
   int kernel;            // 0 Yukawa, 1 Laplace
   int p;                 // expansion order of the tree
   double kappa;
-  const double* A;       // Yukawa coefficients [P1][P1][P1][P1]
+  const double* A;       // packed Yukawa coefficients (see Aoff)
+  const int* Aoff;       // offsets [P1][P1][P1]
+  int nA;                // entries of A
   const double* AL;      // Laplace coefficients [3][P1][P1][P1]
   const double* J;       // packed J_l blocks
   const int* Joff;
+  const double* jval;    // sparse rows of J and J^T (values)
+  const int* jrow;       // [2][L][2]: offset, first column | count << 8 | step << 16
+  int njval;
   const double* center;  // [nn][3]
   const double* radius;  // [nn]
   const double* kR;      // [nn][P1]: k_l(kappa R_node)
@@ -43,10 +48,26 @@ struct TransScratch {
   double ang[4];
 };
 
+// Synchronisation of the lanes cooperating on one translation: the whole block, or
+// only the wavefront when every wavefront of the block works on its own translation.
+template <bool WAVE>
+__device__ __forceinline__ void tsync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+template <bool WAVE> __device__ __forceinline__ int tlane() { return WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
+template <bool WAVE> __device__ __forceinline__ int tstride() { return WAVE ? 64 : (int)blockDim.x; }
+
+template <bool WAVE>
 __device__ __forceinline__ void zrot_inplace(double* c, int pdeg, double alpha) {
   // c'_m = c_m cos(m a) - c_-m sin(m a), c'_-m = c_m sin(m a) + c_-m cos(m a)
   const int npairs = pdeg * (pdeg + 1) / 2;  // (l, m>0) pairs
-  for (int t = threadIdx.x; t < npairs; t += blockDim.x) {
+  for (int t = tlane<WAVE>(); t < npairs; t += tstride<WAVE>()) {
     int l = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5) + 1;
     while (l * (l - 1) / 2 > t) --l;
     while ((l + 1) * l / 2 <= t) ++l;
@@ -60,9 +81,10 @@ __device__ __forceinline__ void zrot_inplace(double* c, int pdeg, double alpha) 
 }
 
 // out = J in (trans = 0) or J^T in (trans = 1), block-diagonal in l
+template <bool WAVE>
 __device__ __forceinline__ void japply(const FmmDev& f, const double* in, double* out, int pdeg, int trans) {
   const int n = (pdeg + 1) * (pdeg + 1);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+  for (int t = tlane<WAVE>(); t < n; t += tstride<WAVE>()) {
     const int l = (int)sqrt((double)t + 0.5);
     const int mo = t - l * l - l;
     const int w = 2 * l + 1;
@@ -110,9 +132,10 @@ __device__ __forceinline__ void kbes_all(double z, int nmax, double* k) {
 // Translation (kind 0 M2M, 1 M2L, 2 L2L) from node S to node T of the expansion in
 // sc.b0 (degree ps; degree pt when transposed); the result is added to acc
 // (degree pt; ps when transposed).  All lanes of the block must call it.
-__device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int pt, int transposed, TransScratch& sc,
-                          double* acc) {
-  if (threadIdx.x == 0) {
+template <bool WAVE>
+__device__ void translate(const FmmDev& f, const double* __restrict__ Atab, int kind, int S, int T, int ps, int pt,
+                          int transposed, TransScratch& sc, double* acc) {
+  if (tlane<WAVE>() == 0) {
     double d[3], rho2 = 0.0;
     for (int a = 0; a < 3; ++a) { d[a] = f.center[3 * T + a] - f.center[3 * S + a]; rho2 += d[a] * d[a]; }
     double rho = sqrt(rho2);
@@ -149,22 +172,22 @@ __device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int p
       for (int k = 0; k <= nmax + 1; ++k) { sc.pw1[k] = v1; sc.pw2[k] = v2; v1 *= a1; v2 *= a2; }
     }
   }
-  __syncthreads();
+  tsync<WAVE>();
   const double th = sc.ang[0], ph = sc.ang[1];
   const int pin = transposed ? pt : ps, pout = transposed ? ps : pt;
   // rotate the input to the frame where the target sits on the -z axis
-  zrot_inplace(sc.b0, pin, -ph);
-  __syncthreads();
-  japply(f, sc.b0, sc.b1, pin, 0);
-  __syncthreads();
-  zrot_inplace(sc.b1, pin, 3.141592653589793 - th);
-  __syncthreads();
-  japply(f, sc.b1, sc.b0, pin, 1);
-  __syncthreads();
+  zrot_inplace<WAVE>(sc.b0, pin, -ph);
+  tsync<WAVE>();
+  japply<WAVE>(f, sc.b0, sc.b1, pin, 0);
+  tsync<WAVE>();
+  zrot_inplace<WAVE>(sc.b1, pin, 3.141592653589793 - th);
+  tsync<WAVE>();
+  japply<WAVE>(f, sc.b1, sc.b0, pin, 1);
+  tsync<WAVE>();
   // translation along z
   const int P1 = f.p + 1;
   const int nout = (pout + 1) * (pout + 1);
-  for (int t = threadIdx.x; t < nout; t += blockDim.x) {
+  for (int t = tlane<WAVE>(); t < nout; t += tstride<WAVE>()) {
     const int lo = (int)sqrt((double)t + 0.5);
     const int m = t - lo * lo - lo, am = abs(m);
     double s = 0.0;
@@ -173,7 +196,7 @@ __device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int p
       const int lp = transposed ? li : lo;  // target degree
       double e;
       if (f.kernel == 0) {
-        const double* Ar = f.A + (((size_t)l * P1 + lp) * P1 + am) * P1;
+        const double* Ar = Atab + f.Aoff[((size_t)l * P1 + lp) * P1 + am] - am;
         double sk = 0.0;
         const int kmax = min(l, lp);
         if (kind == 1) {
@@ -184,7 +207,7 @@ __device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int p
           e = sk * sc.radT[lp] * sc.radS[l] * ((kind == 2 && ((l + lp) & 1)) ? -1.0 : 1.0);
         }
       } else {
-        const double a = f.AL[(size_t)kind * P1 * P1 * P1 + ((size_t)l * P1 + lp) * P1 + am];
+        const double a = Atab[((size_t)l * P1 + lp) * P1 + am];
         if (a == 0.0) continue;
         if (kind == 0) e = a * sc.pw1[l + 1] * sc.pw2[lp - l];
         else if (kind == 1) e = a * sc.pw1[lp] * sc.pw2[l + 1];
@@ -194,18 +217,24 @@ __device__ void translate(const FmmDev& f, int kind, int S, int T, int ps, int p
     }
     sc.b1[t] = s;
   }
-  __syncthreads();
+  tsync<WAVE>();
   // rotate back
-  japply(f, sc.b1, sc.b0, pout, 0);
-  __syncthreads();
-  zrot_inplace(sc.b0, pout, th - 3.141592653589793);
-  __syncthreads();
-  japply(f, sc.b0, sc.b1, pout, 1);
-  __syncthreads();
-  zrot_inplace(sc.b1, pout, ph);
-  __syncthreads();
-  for (int t = threadIdx.x; t < nout; t += blockDim.x) acc[t] += sc.b1[t];
-  __syncthreads();
+  japply<WAVE>(f, sc.b1, sc.b0, pout, 0);
+  tsync<WAVE>();
+  zrot_inplace<WAVE>(sc.b0, pout, th - 3.141592653589793);
+  tsync<WAVE>();
+  japply<WAVE>(f, sc.b0, sc.b1, pout, 1);
+  tsync<WAVE>();
+  zrot_inplace<WAVE>(sc.b1, pout, ph);
+  tsync<WAVE>();
+  for (int t = tlane<WAVE>(); t < nout; t += tstride<WAVE>()) acc[t] += sc.b1[t];
+  tsync<WAVE>();
+}
+
+// coefficient table of a kernel type and translation kind, in global memory
+__device__ __forceinline__ const double* coef_table(const FmmDev& f, int kind) {
+  const int P1 = f.p + 1;
+  return f.kernel == 0 ? f.A : f.AL + (size_t)kind * P1 * P1 * P1;
 }
 
 // per-node Bessel scales k_l(kappa R), i_l(kappa R), l = 0..p
@@ -259,7 +288,7 @@ __global__ __launch_bounds__(64) void k_fmm_upward(FmmDev f, const int* __restri
     __syncthreads();
     for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
     __syncthreads();
-    translate(f, 0, ch, n, f.p, f.p, 0, sc, acc);
+    translate<false>(f, coef_table(f, 0), 0, ch, n, f.p, f.p, 0, sc, acc);
   }
   for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] = acc[t];
 }
@@ -279,13 +308,237 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __r
       __syncthreads();
       for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = Ein[(long)o * P + t];
       __syncthreads();
-      if (!transposed) translate(f, 1, o, n, f.p, f.p, 0, sc, acc);
-      else translate(f, 1, n, o, f.p, f.p, 1, sc, acc);
+      if (!transposed) translate<false>(f, coef_table(f, 1), 1, o, n, f.p, f.p, 0, sc, acc);
+      else translate<false>(f, coef_table(f, 1), 1, n, o, f.p, f.p, 1, sc, acc);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < P; t += blockDim.x) Eout[(long)n * P + t] = acc[t];
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Multipole-to-local, one wavefront per translation, every table in LDS.
+//
+// Same operator as translate(kind 1) with the work laid out for a wavefront:
+//   * the rotation angles enter only through cos/sin of m*phi and m*theta, taken as
+//     integer powers of the unit complex numbers built from the centre offset
+//     (no trigonometric calls);
+//   * J and J^T are applied through their sparse rows (a quarter of the entries);
+//   * the z translation is computed once per (l_out, |m|) and applied to +m and -m;
+//   * the first rotation is fused with the load of the input expansion and the last
+//     one with the accumulation.
+// LDS: the tables (shared by the block) followed by one scratch area per wavefront.
+__device__ __forceinline__ double ipow_d(double b, int e) {
+  double r = 1.0;
+  while (e) {
+    if (e & 1) r *= b;
+    b *= b;
+    e >>= 1;
+  }
+  return r;
+}
+__device__ __forceinline__ void cpow_d(double c, double s, int e, double& rc, double& rs) {
+  double xc = 1.0, xs = 0.0;
+  while (e) {
+    if (e & 1) { const double t = xc * c - xs * s; xs = xc * s + xs * c; xc = t; }
+    const double t = c * c - s * s;
+    s = 2.0 * c * s;
+    c = t;
+    e >>= 1;
+  }
+  rc = xc;
+  rs = xs;
+}
+
+__host__ __device__ constexpr int m2l_fast_wave_doubles(int p) { return 3 * (p + 1) * (p + 1) + 12 * (p + 1); }
+
+// J (mat 0) or J^T (mat 1) applied to src, written to dst (degree p)
+__device__ __forceinline__ void japply_sparse(const double* __restrict__ jv, const int* __restrict__ jr, int mat, int P,
+                                              const double* src, double* dst, int lane) {
+  for (int t = lane; t < P; t += 64) {
+    const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
+    const int l = (int)sqrtf((float)t + 0.5f);
+    const int c0 = d & 255, cnt = (d >> 8) & 255, st = d >> 16;
+    const double* x = src + l * l + c0;
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += jv[off + k] * x[st * k];
+    dst[t] = s;
+  }
+}
+
+template <bool ALDS>
+__global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, int nn, const int* __restrict__ lptr,
+                                                       const int* __restrict__ lidx, int transposed,
+                                                       const double* __restrict__ Ein, double* __restrict__ Eout) {
+  extern __shared__ double smem[];
+  const int p = f.p, P1 = p + 1, P = P1 * P1;
+  const int nw = blockDim.x >> 6;
+  const int nat = f.kernel == 0 ? f.nA : P1 * P1 * P1;
+  const int naoff = (ALDS && f.kernel == 0) ? P1 * P1 * P1 : 0;
+  // block-shared tables
+  double* jv = smem;
+  double* at = jv + f.njval;
+  double* wsb = at + (ALDS ? nat : 0);
+  int* jr = (int*)(wsb + nw * m2l_fast_wave_doubles(p));
+  int* ao = jr + 4 * P;
+  const double* gt = coef_table(f, 1);
+  for (int t = threadIdx.x; t < f.njval; t += blockDim.x) jv[t] = f.jval[t];
+  for (int t = threadIdx.x; t < 4 * P; t += blockDim.x) jr[t] = f.jrow[t];
+  if constexpr (ALDS) {
+    for (int t = threadIdx.x; t < nat; t += blockDim.x) at[t] = gt[t];
+    for (int t = threadIdx.x; t < naoff; t += blockDim.x) ao[t] = f.Aoff[t];
+  }
+  __syncthreads();
+  const double* A;
+  const int* AO;
+  if constexpr (ALDS) { A = at; AO = ao; } else { A = gt; AO = f.Aoff; }
+
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* b0 = wsb + w * m2l_fast_wave_doubles(p);
+  double* b1 = b0 + P;
+  double* acc = b1 + P;
+  double* bes = acc + P;       // 2p+2
+  double* pw1 = bes + 2 * P1;  // 2p+2
+  double* pw2 = pw1 + 2 * P1;  // 2p+2
+  double* radS = pw2 + 2 * P1;
+  double* radT = radS + P1;
+  double* cph = radT + P1;
+  double* sph = cph + P1;
+  double* cth = sph + P1;
+  double* sth = cth + P1;
+  const int npair = P1 * (P1 + 1) / 2;
+
+  for (int n = blockIdx.x * nw + w; n < nn; n += gridDim.x * nw) {
+    for (int t = lane; t < P; t += 64) acc[t] = 0.0;
+    for (int q = lptr[n]; q < lptr[n + 1]; ++q) {
+      const int o = lidx[q];
+      const int S = transposed ? n : o, T = transposed ? o : n;
+      const double dx = f.center[3 * T] - f.center[3 * S], dy = f.center[3 * T + 1] - f.center[3 * S + 1],
+                   dz = f.center[3 * T + 2] - f.center[3 * S + 2];
+      const double rxy = sqrt(dx * dx + dy * dy), rho = sqrt(dx * dx + dy * dy + dz * dz);
+      tsync<true>();  // previous translation done with the per-translation tables
+      if (lane <= p) {
+        double c1 = 1.0, s1 = 0.0;
+        if (rxy > 0.0) { c1 = dx / rxy; s1 = dy / rxy; }
+        cpow_d(c1, s1, lane, cph[lane], sph[lane]);
+        cpow_d(dz / rho, rxy / rho, lane, cth[lane], sth[lane]);
+        if (f.kernel == 0) {
+          radS[lane] = 1.0 / f.kR[S * P1 + lane];
+          radT[lane] = f.iR[T * P1 + lane];
+        }
+      }
+      if (f.kernel == 0) {
+        const double z = f.kappa * rho;
+        if (lane <= 2 * p) {
+          // k_n(z) = (pi/2) e^-z / z sum_j (n+j)! / (j! (n-j)!) (2z)^-j
+          const int nb = lane;
+          const double h = 0.5 / z;
+          double term = 1.0, sum = 1.0;
+          for (int j = 0; j < nb; ++j) {
+            term *= (double)(nb + j + 1) * (double)(nb - j) / (double)(j + 1) * h;
+            sum += term;
+          }
+          bes[lane] = 1.5707963267948966 * exp(-z) / z * sum;
+          pw1[lane] = ipow_d(-1.0 / z, lane);
+        }
+      } else if (lane <= p + 1) {
+        pw1[lane] = ipow_d(f.radius[T] / rho, lane);
+        pw2[lane] = ipow_d(f.radius[S] / rho, lane);
+      }
+      tsync<true>();
+      // input, rotated by -phi about z
+      const double* src = Ein + (long)o * P;
+      for (int t = lane; t < P; t += 64) {
+        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
+        if (m == 0) b0[t] = src[t];
+        else if (m > 0) {
+          const double a = src[t], b = src[t - 2 * m], co = cph[m], si = -sph[m];
+          b0[t] = a * co - b * si;
+          b0[t - 2 * m] = a * si + b * co;
+        }
+      }
+      tsync<true>();
+      japply_sparse(jv, jr, 0, P, b0, b1, lane);
+      tsync<true>();
+      // rotation by pi - theta: cos = (-1)^m cos(m theta), sin = -(-1)^m sin(m theta)
+      for (int t = lane; t < P; t += 64) {
+        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
+        if (m > 0) {
+          const double sg = (m & 1) ? -1.0 : 1.0;
+          const double a = b1[t], b = b1[t - 2 * m], co = sg * cth[m], si = -sg * sth[m];
+          b1[t] = a * co - b * si;
+          b1[t - 2 * m] = a * si + b * co;
+        }
+      }
+      tsync<true>();
+      japply_sparse(jv, jr, 1, P, b1, b0, lane);
+      tsync<true>();
+      // translation along z: one (l_out, |m|) pair per lane, applied to +m and -m
+      for (int u = lane; u < npair; u += 64) {
+        int lo = (int)((sqrtf(8.0f * u + 1.0f) - 1.0f) * 0.5f);
+        while (lo * (lo + 1) / 2 > u) --lo;
+        while ((lo + 1) * (lo + 2) / 2 <= u) ++lo;
+        const int am = u - lo * (lo + 1) / 2;
+        double sp = 0.0, sm = 0.0;
+        for (int li = am; li <= p; ++li) {
+          const int l = transposed ? lo : li, lp = transposed ? li : lo;
+          double e;
+          if (f.kernel == 0) {
+            const double* Ar = A + AO[(l * P1 + lp) * P1 + am] - am;
+            const int kmax = min(l, lp);
+            double sk = 0.0;
+            for (int k = am; k <= kmax; ++k) sk += Ar[k] * bes[l + lp - k] * pw1[k];
+            e = sk * radT[lp] * radS[l];
+            if (l & 1) e = -e;
+          } else {
+            e = A[(l * P1 + lp) * P1 + am] * pw1[lp] * pw2[l + 1];
+          }
+          sp += e * b0[li * li + li + am];
+          sm += e * b0[li * li + li - am];
+        }
+        b1[lo * lo + lo + am] = sp;
+        if (am) b1[lo * lo + lo - am] = sm;
+      }
+      tsync<true>();
+      japply_sparse(jv, jr, 0, P, b1, b0, lane);
+      tsync<true>();
+      // rotation by theta - pi: cos = (-1)^m cos(m theta), sin = (-1)^m sin(m theta)
+      for (int t = lane; t < P; t += 64) {
+        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
+        if (m > 0) {
+          const double sg = (m & 1) ? -1.0 : 1.0;
+          const double a = b0[t], b = b0[t - 2 * m], co = sg * cth[m], si = sg * sth[m];
+          b0[t] = a * co - b * si;
+          b0[t - 2 * m] = a * si + b * co;
+        }
+      }
+      tsync<true>();
+      japply_sparse(jv, jr, 1, P, b0, b1, lane);
+      tsync<true>();
+      // rotation by phi, accumulated
+      for (int t = lane; t < P; t += 64) {
+        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
+        if (m == 0) acc[t] += b1[t];
+        else if (m > 0) {
+          const double a = b1[t], b = b1[t - 2 * m], co = cph[m], si = sph[m];
+          acc[t] += a * co - b * si;
+          acc[t - 2 * m] += a * si + b * co;
+        }
+      }
+    }
+    tsync<true>();
+    for (int t = lane; t < P; t += 64) Eout[(long)n * P + t] = acc[t];
+  }
+}
+
+// LDS bytes of k_fmm_m2l_fast for nw wavefronts per block
+inline size_t m2l_fast_lds_bytes(int kernel, int p, int nA, int njval, int nw, bool alds) {
+  const size_t P1 = p + 1, P = P1 * P1;
+  const size_t nat = kernel == 0 ? (size_t)nA : P1 * P1 * P1;
+  size_t d = (size_t)njval + (alds ? nat : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
+  size_t i = 4 * P + ((alds && kernel == 0) ? P1 * P1 * P1 : 0);
+  return d * sizeof(double) + i * sizeof(int);
 }
 
 // downward pass of one level: L[n] += L2L(parent -> n) L[parent]
@@ -301,8 +554,8 @@ __global__ __launch_bounds__(64) void k_fmm_downward(FmmDev f, const int* __rest
   const int P = (f.p + 1) * (f.p + 1);
   for (int t = threadIdx.x; t < P; t += blockDim.x) { acc[t] = 0.0; sc.b0[t] = E[(long)par * P + t]; }
   __syncthreads();
-  if (!transposed) translate(f, 2, par, n, f.p, f.p, 0, sc, acc);
-  else translate(f, 0, n, par, f.p, f.p, 1, sc, acc);
+  if (!transposed) translate<false>(f, coef_table(f, 2), 2, par, n, f.p, f.p, 0, sc, acc);
+  else translate<false>(f, coef_table(f, 0), 0, n, par, f.p, f.p, 1, sc, acc);
   for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
 }
 
@@ -321,7 +574,7 @@ __global__ __launch_bounds__(64) void k_fmm_upward_T(FmmDev f, const int* __rest
     __syncthreads();
     for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
     __syncthreads();
-    translate(f, 2, n, ch, f.p, f.p, 1, sc, acc);
+    translate<false>(f, coef_table(f, 2), 2, n, ch, f.p, f.p, 1, sc, acc);
   }
   for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
 }

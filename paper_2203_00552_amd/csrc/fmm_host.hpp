@@ -174,9 +174,18 @@ struct Tables {
   std::vector<double> A;
   // Laplace: per kind (0 m2m, 1 m2l, 2 l2l): AL[kind][(l*(P1) + l')*(P1) + |m|]
   std::vector<double> AL;
+  // packed Yukawa coefficients: Ap[Aoff[(l*P1 + l')*P1 + |m|] + (k - |m|)], k = |m|..min(l, l')
+  std::vector<double> Ap;
+  std::vector<int> Aoff;
   // rotation by +90 degrees about x: packed blocks J_l [(2l+1)^2], row m'+l, column m+l
   std::vector<double> J;
   std::vector<int> Joff;
+  // Sparse rows of J (mat 0) and J^T (mat 1).  Every row of a block has its nonzeros
+  // on every second column of one run (the blocks split by the parity classes of m):
+  // Jrow[2 * (mat * L + t)] = offset into Jval, Jrow[2 * (mat * L + t) + 1] =
+  // first column (m + l) | count << 8 | column step << 16, row t = l^2 + l + m'.
+  std::vector<double> Jval;
+  std::vector<int> Jrow;
 };
 
 inline void build_tables(int pmax, Tables& tb) {
@@ -202,6 +211,14 @@ inline void build_tables(int pmax, Tables& tb) {
           tb.AL[2 * (size_t)P1 * P1 * P1 + o] = c * clmk(l, am, lp, lp) * (((l + lp) % 2) ? -1.0 : 1.0) * dfact(2 * l + 1) /
                                                  (dfact(2 * lp + 1) * dfact(2 * l + 1));
       }
+  tb.Aoff.assign((size_t)P1 * P1 * P1, 0);
+  tb.Ap.clear();
+  for (int l = 0; l <= pmax; ++l)
+    for (int lp = 0; lp <= pmax; ++lp)
+      for (int am = 0; am <= std::min(l, lp); ++am) {
+        tb.Aoff[((size_t)l * P1 + lp) * P1 + am] = (int)tb.Ap.size();
+        for (int k = am; k <= std::min(l, lp); ++k) tb.Ap.push_back(tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k]);
+      }
   // J_l[m', m] = sum_n w_n Y_lm'(s_n) Y_lm(Q^T s_n), Q = rotation by +90 degrees about x,
   // exact for a Lebedev rule of degree >= 2 pmax.
   const auto* rule = host::lebedev_rule_min_degree(2 * pmax);
@@ -220,6 +237,35 @@ inline void build_tables(int pmax, Tables& tb) {
         for (int b = -l; b <= l; ++b)
           tb.J[tb.Joff[l] + (a + l) * (2 * l + 1) + (b + l)] += s[3] * Y[host::lmi(l, a)] * YQ[host::lmi(l, b)];
   }
+  // entries that vanish by symmetry come out of the quadrature at rounding level
+  for (double& v : tb.J)
+    if (std::fabs(v) < 1e-12) v = 0.0;
+  tb.Jval.clear();
+  tb.Jrow.assign((size_t)4 * L, 0);
+  for (int mat = 0; mat < 2; ++mat)
+    for (int l = 0; l <= pmax; ++l) {
+      const int w = 2 * l + 1;
+      for (int a = 0; a < w; ++a) {
+        std::vector<int> cols;
+        for (int b = 0; b < w; ++b) {
+          const double v = mat == 0 ? tb.J[tb.Joff[l] + a * w + b] : tb.J[tb.Joff[l] + b * w + a];
+          if (v != 0.0) cols.push_back(b);
+        }
+        if (cols.empty()) cols.push_back(0);
+        // one run of step 2 when every nonzero has the parity of the first (accidental
+        // zeros inside the run are stored), else the dense row
+        int step = 2;
+        for (int b : cols)
+          if ((b - cols[0]) % 2) step = 1;
+        const int first = step == 2 ? cols.front() : 0, last = step == 2 ? cols.back() : w - 1;
+        cols.clear();
+        for (int b = first; b <= last; b += step) cols.push_back(b);
+        const size_t t = (size_t)l * l + a;
+        tb.Jrow[2 * (mat * L + t)] = (int)tb.Jval.size();
+        tb.Jrow[2 * (mat * L + t) + 1] = cols[0] | ((int)cols.size() << 8) | (step << 16);
+        for (int b : cols) tb.Jval.push_back(mat == 0 ? tb.J[tb.Joff[l] + a * w + b] : tb.J[tb.Joff[l] + b * w + a]);
+      }
+    }
 }
 
 }  // namespace fmm

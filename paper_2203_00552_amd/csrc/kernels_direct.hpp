@@ -650,3 +650,265 @@ __global__ __launch_bounds__(1024) void k_energy(int M, int L, const double* __r
 }
 
 }  // namespace ddlpb
+
+namespace ddlpb {
+
+// ------------------------------------------------------------ cap lists
+// Caps: (i, n, j) with |x_i^n - x_j| < r_j, stored per sphere i sorted by (n, j):
+// cap_n, cap_slot (position of j in N_i), cap_w (omega_ij(x_i^n)); per-point ranges pcp[i*(N+1)+n].
+// Reverse caps per sphere j: (i, n, omega) with j in N_i, sorted by (i, n).
+__global__ void k_caps_fill(int M, int N, const double* __restrict__ xyz, const double* __restrict__ rad,
+                            const double* __restrict__ leb, const int* __restrict__ nptr, const int* __restrict__ nidx,
+                            const double* __restrict__ f, double eta, const int* __restrict__ cptr,
+                            int* __restrict__ cap_n, int* __restrict__ cap_slot, double* __restrict__ cap_w,
+                            int* __restrict__ pcp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int c = cptr[i];
+  for (int n = 0; n < N; ++n) {
+    pcp[(long)i * (N + 1) + n] = c;
+    const double px = xyz[3 * i] + rad[i] * leb[4 * n], py = xyz[3 * i + 1] + rad[i] * leb[4 * n + 1],
+                 pz = xyz[3 * i + 2] + rad[i] * leb[4 * n + 2];
+    const double fv = f[(long)i * N + n];
+    const double dfac = fv > 1.0 ? 1.0 / fv : 1.0;
+    for (int a = nptr[i]; a < nptr[i + 1]; ++a) {
+      const int j = nidx[a];
+      const double dx = px - xyz[3 * j], dy = py - xyz[3 * j + 1], dz = pz - xyz[3 * j + 2];
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 < rad[j] * rad[j]) {
+        cap_n[c] = n;
+        cap_slot[c] = a - nptr[i];
+        cap_w[c] = dfac * chi_eta(sqrt(d2) / rad[j], eta);
+        ++c;
+      }
+    }
+  }
+  pcp[(long)i * (N + 1) + N] = c;
+}
+// reverse caps: count per j then fill (deterministic order: i ascending in N_j, then n)
+__global__ void k_rcaps_count(int M, int N, const double* __restrict__ xyz, const double* __restrict__ rad,
+                              const double* __restrict__ leb, const int* __restrict__ nptr,
+                              const int* __restrict__ nidx, int* __restrict__ cnt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int c = 0;
+  for (int a = nptr[j]; a < nptr[j + 1]; ++a) {
+    const int i = nidx[a];
+    for (int n = 0; n < N; ++n) {
+      const double dx = xyz[3 * i] + rad[i] * leb[4 * n] - xyz[3 * j], dy = xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - xyz[3 * j + 1],
+                   dz = xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - xyz[3 * j + 2];
+      c += (dx * dx + dy * dy + dz * dz < rad[j] * rad[j]);
+    }
+  }
+  cnt[j] = c;
+}
+__global__ void k_rcaps_fill(int M, int N, const double* __restrict__ xyz, const double* __restrict__ rad,
+                             const double* __restrict__ leb, const int* __restrict__ nptr, const int* __restrict__ nidx,
+                             const double* __restrict__ f, double eta, const int* __restrict__ rptr,
+                             int* __restrict__ rc_i, int* __restrict__ rc_n, double* __restrict__ rc_w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int c = rptr[j];
+  for (int a = nptr[j]; a < nptr[j + 1]; ++a) {
+    const int i = nidx[a];
+    for (int n = 0; n < N; ++n) {
+      const double dx = xyz[3 * i] + rad[i] * leb[4 * n] - xyz[3 * j], dy = xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - xyz[3 * j + 1],
+                   dz = xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - xyz[3 * j + 2];
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 < rad[j] * rad[j]) {
+        const double fv = f[(long)i * N + n];
+        rc_i[c] = i;
+        rc_n[c] = n;
+        rc_w[c] = (fv > 1.0 ? 1.0 / fv : 1.0) * chi_eta(sqrt(d2) / rad[j], eta);
+        ++c;
+      }
+    }
+  }
+}
+
+// ------------------------------------------- apply L (near part) from cap lists
+// Same result as k_apply_LX: one block per sphere i; the coefficients of the
+// neighbours are staged in LDS, every thread evaluates whole caps, per-point sums
+// are taken in cap order (deterministic), then the An transforms.
+constexpr int kCapChunk = 512;
+constexpr int kNbrLds = 16;
+template <int LM>
+__global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, const double* __restrict__ Y,
+                                                        const double* __restrict__ leb, const double* __restrict__ xyz,
+                                                        const double* __restrict__ rad, const int* __restrict__ nptr,
+                                                        const int* __restrict__ nidx, const int* __restrict__ cptr,
+                                                        const int* __restrict__ cap_n, const int* __restrict__ cap_slot,
+                                                        const double* __restrict__ cap_w, const int* __restrict__ pcp,
+                                                        const double* __restrict__ U, const double* __restrict__ sgr,
+                                                        int LUR, double kappa, int nterms,
+                                                        const double* __restrict__ base, double c0,
+                                                        const double* __restrict__ nearX, double c1,
+                                                        const double* __restrict__ gr1, const double* __restrict__ gr2,
+                                                        const double* __restrict__ ge, double cg,
+                                                        double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double vA[kMaxN], vB[kMaxN], gR[kMaxN], gE[kMaxN];
+  __shared__ double capA[kCapChunk], capB[kCapChunk];
+  __shared__ double sX[kNbrLds * 2 * L];
+  const int i = blockIdx.x;
+  const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2], ri = rad[i];
+  const int q0 = nptr[i], K = nptr[i + 1] - q0;
+  const bool lds_x = K <= kNbrLds;
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    vA[n] = 0.0;
+    vB[n] = 0.0;
+    const double u = U[(long)i * N + n];
+    gR[n] = gr1 ? u * (gr1[(long)i * N + n] + (gr2 ? gr2[(long)i * N + n] : 0.0)) : 0.0;
+    gE[n] = ge ? u * ge[(long)i * N + n] : 0.0;
+  }
+  if (nearX && lds_x) {
+    for (int t = threadIdx.x; t < K * 2 * L; t += blockDim.x) {
+      const int a = t / (2 * L), r = t - a * 2 * L;
+      const int j = nidx[q0 + a];
+      sX[t] = r < L ? nearX[(long)j * L + r] : nearX[(long)(M + j) * L + r - L];
+    }
+  }
+  __syncthreads();
+  if (nearX) {
+    const int c0i = cptr[i], c1i = cptr[i + 1];
+    for (int cb = c0i; cb < c1i; cb += kCapChunk) {
+      const int ce = min(c1i, cb + kCapChunk);
+      for (int c = cb + threadIdx.x; c < ce; c += blockDim.x) {
+        const int n = cap_n[c], a = cap_slot[c];
+        const int j = nidx[q0 + a];
+        const double irj = 1.0 / rad[j];
+        const double vx = (xi + ri * leb[4 * n] - xyz[3 * j]) * irj, vy = (yi + ri * leb[4 * n + 1] - xyz[3 * j + 1]) * irj,
+                     vz = (zi + ri * leb[4 * n + 2] - xyz[3 * j + 2]) * irj;
+        const double t2 = vx * vx + vy * vy + vz * vz;
+        double sg[LM + 1];
+        sigma_weights<LM, double>(kappa * kappa * rad[j] * rad[j] * t2, nterms, sg);
+        const double* Xr = lds_x ? sX + a * 2 * L : nearX + (long)j * L;
+        const double* Xe = lds_x ? sX + a * 2 * L + L : nearX + (long)(M + j) * L;
+        double sa = 0.0, pb[LM + 1];
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) pb[l] = 0.0;
+        for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
+          sa += Xr[idx] * S;
+          pb[l] += Xe[idx] * S;
+        });
+        double sb = 0.0;
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] / sgr[j * LUR + l];
+        const double w = cap_w[c];
+        capA[c - cb] = w * sa;
+        capB[c - cb] = w * sb;
+      }
+      __syncthreads();
+      for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int p0 = max(pcp[(long)i * (N + 1) + n], cb), p1 = min(pcp[(long)i * (N + 1) + n + 1], ce);
+        double a = 0.0, b = 0.0;
+        for (int c = p0; c < p1; ++c) { a += capA[c - cb]; b += capB[c - cb]; }
+        vA[n] += a;
+        vB[n] += b;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double sa = 0.0, sb = 0.0, sr = 0.0, se = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double wy = leb[4 * n + 3] * Y[(long)n * LY + t];
+      sa += wy * vA[n];
+      sb += wy * vB[n];
+      sr += wy * gR[n];
+      se += wy * gE[n];
+    }
+    const long ir = (long)i * L + t, ie = (long)(M + i) * L + t;
+    double orr = c1 * sa + cg * sr, oe = c1 * sb + cg * se;
+    if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
+    out[ir] = orr;
+    out[ie] = oe;
+  }
+}
+
+// Transposed near part from reverse cap lists (same result as the near part of k_apply_LTZ).
+template <int LM>
+__global__ __launch_bounds__(256) void k_apply_LTZ_caps(int M, int N, int LY, const double* __restrict__ Y,
+                                                         const double* __restrict__ leb, const double* __restrict__ xyz,
+                                                         const double* __restrict__ rad, const int* __restrict__ rptr,
+                                                         const int* __restrict__ rc_i, const int* __restrict__ rc_n,
+                                                         const double* __restrict__ rc_w, const double* __restrict__ U,
+                                                         const double* __restrict__ sgr, const double* __restrict__ ycr,
+                                                         const double* __restrict__ yce, const double* __restrict__ Cl,
+                                                         int LUR, double kappa, int nterms,
+                                                         const double* __restrict__ base, double c0,
+                                                         const double* __restrict__ zr, const double* __restrict__ ze,
+                                                         double c1, const double* __restrict__ lam, int LLAM,
+                                                         double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double gg[kMaxN];
+  __shared__ double cl[L], mu[L];
+  __shared__ double red[8 * L];
+  const int j = blockIdx.x;
+  if (lam) {
+    for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t];
+    __syncthreads();
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      const double* Yn = Y + (long)n * LY;
+      double a = 0.0;
+      for (int t = 0; t < L; ++t) a += Yn[t] * cl[t];
+      gg[n] = U[(long)j * N + n] * a;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+      double a = 0.0;
+      for (int n = 0; n < N; ++n) a += leb[4 * n + 3] * Y[(long)n * LY + t] * gg[n];
+      mu[t] = a;
+    }
+  } else {
+    for (int t = threadIdx.x; t < L; t += blockDim.x) mu[t] = 0.0;
+  }
+  double accA[L], accB[L];
+#pragma unroll
+  for (int t = 0; t < L; ++t) { accA[t] = 0.0; accB[t] = 0.0; }
+  if (zr) {
+    const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
+    double isg[LM + 1];
+#pragma unroll
+    for (int l = 0; l <= LM; ++l) isg[l] = 1.0 / sgr[j * LUR + l];
+    for (int c = rptr[j] + threadIdx.x; c < rptr[j + 1]; c += blockDim.x) {
+      const int i = rc_i[c], n = rc_n[c];
+      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const double t2 = vx * vx + vy * vy + vz * vz;
+      const double wom = leb[4 * n + 3] * rc_w[c];
+      const double cA = wom * zr[(long)i * N + n], cB = wom * ze[(long)i * N + n];
+      double sg[LM + 1];
+      sigma_weights<LM, double>(kappa * kappa * rj * rj * t2, nterms, sg);
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) sg[l] *= cB * isg[l];
+      for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
+        accA[idx] += cA * S;
+        accB[idx] += sg[l] * S;
+      });
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    double a = wave_sum(accA[t]);
+    double b = wave_sum(accB[t]);
+    if (lane == 0) { red[wid * 2 * L + t] = a; red[wid * 2 * L + L + t] = b; }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < nw; ++w) { a += red[w * 2 * L + t]; b += red[w * 2 * L + L + t]; }
+    const int l = deg_of(t);
+    const long ir = (long)j * L + t, ie = (long)(M + j) * L + t;
+    double orr = c1 * a + ycr[j * LUR + l] * mu[t];
+    double oe = c1 * b + yce[j * LUR + l] * mu[t];
+    if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
+    out[ir] = orr;
+    out[ie] = oe;
+  }
+}
+
+}  // namespace ddlpb

@@ -49,6 +49,35 @@ def test_fmm_adjoint_is_exact_transpose(cluster):
     assert abs(a - b) < 1e-11 * abs(a)
 
 
+def test_m2l_block_layouts_agree(cluster):
+    """The multipole-to-local kernel gives the same result for every block layout
+    (wavefronts per block, coefficient tables in LDS or global memory)."""
+    x, r, q = cluster
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(2, len(r), 49))
+    out = []
+    for w in (1, 4, 16):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=10, options={"m2l_waves": w})
+        out.append((f.apply(X), f.apply(X, transpose=True)))
+    for a, b in out[1:]:
+        assert _rel(a, out[0][0]) < 1e-13 and _rel(b, out[0][1]) < 1e-13
+
+
+def test_fmm_error_decreases_with_order(cluster):
+    """At a fixed acceptance parameter the far-field error falls with the expansion
+    order (the local expansions are evaluated on the sphere grids to full degree p)."""
+    x, r, q = cluster
+    d = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=0)
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(2, len(r), 49)) * np.exp(-0.4 * np.repeat(np.arange(7), 2 * np.arange(7) + 1))
+    Yd = d.apply(X)
+    errs = []
+    for p in (8, 11, 14):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=p, options={"theta": 0.7})
+        errs.append(_rel(f.apply(X), Yd))
+    assert errs[1] < 0.5 * errs[0] and errs[2] < 0.5 * errs[1], errs
+
+
 def test_fmm_rhs_matches_direct(cluster):
     x, r, q = cluster
     d = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=0)
