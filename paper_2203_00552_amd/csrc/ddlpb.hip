@@ -69,6 +69,8 @@ struct ddlpb_ctx {
   bool warm_start = true;
   double theta = 0.5;
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic)
+  int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
+  struct M2LCfg { bool valid = false, alds = false; int nw = 0, per_cu = 0; size_t bytes = 0; } m2l_cfg[2];
   // ---- host analysis
   std::vector<int> nptr, nidx, nrev;
   std::vector<int> pptr, pidx;  // sphere pairs of the near preconditioner (self included)
@@ -109,11 +111,14 @@ struct ddlpb_ctx {
   fmm::Tree tree;
   fmm::Tables tables;
   size_t m2l_cap = 0, near_cap = 0;
-  double *d_fcen = nullptr, *d_frad = nullptr, *d_fkR = nullptr, *d_fiR = nullptr, *d_fA = nullptr, *d_fAL = nullptr,
+  double *d_fcen = nullptr, *d_frad = nullptr, *d_fkR = nullptr, *d_fkRi = nullptr, *d_fiR = nullptr, *d_fA = nullptr, *d_fAL = nullptr,
          *d_fJ = nullptr, *d_Mn = nullptr, *d_Ln = nullptr, *d_SL = nullptr, *d_Lam = nullptr, *d_sgp = nullptr,
          *d_qsrc = nullptr, *d_tmp4 = nullptr;
   double* d_fjval = nullptr;
   int* d_fjrow = nullptr;
+  double* d_fZ[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [kernel][direction]
+  int* d_fZslot[2] = {nullptr, nullptr};
+  int *d_fm2lord = nullptr, *d_fm2ltord = nullptr, *d_fctr = nullptr;
   int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
       *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
       *d_sleaf = nullptr;
@@ -355,6 +360,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
     c->d_fcen = cv.take<double>(3 * nn);
     c->d_frad = cv.take<double>(nn);
     c->d_fkR = cv.take<double>(nn * p1);
+    c->d_fkRi = cv.take<double>(nn * p1);
     c->d_fiR = cv.take<double>(nn * p1);
     c->d_fchild = cv.take<int>(2 * nn);
     c->d_fparent = cv.take<int>(nn);
@@ -373,6 +379,13 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
     c->d_fJoff = cv.take<int>(p1 + 1);
     c->d_fjval = cv.take<double>(std::max<size_t>(c->tables.Jval.size(), 1));
     c->d_fjrow = cv.take<int>(std::max<size_t>(c->tables.Jrow.size(), 1));
+    for (int k = 0; k < 2; ++k) {
+      for (int d = 0; d < 2; ++d) c->d_fZ[k][d] = cv.take<double>(std::max<size_t>(c->tables.Z[k][d].size(), 1));
+      c->d_fZslot[k] = cv.take<int>(std::max<size_t>(c->tables.Zslot[k].size(), 1));
+    }
+    c->d_fm2lord = cv.take<int>(nn);
+    c->d_fm2ltord = cv.take<int>(nn);
+    c->d_fctr = cv.take<int>(64);
     c->d_Mn = cv.take<double>(nn * P);
     c->d_Ln = cv.take<double>(nn * P);
     c->d_SL = cv.take<double>(M * P);
@@ -595,7 +608,8 @@ FmmDev fmm_dev(ddlpb_ctx* c, int kernel) {
   f.A = c->d_fA; f.Aoff = c->d_fAoff; f.nA = (int)c->tables.Ap.size();
   f.AL = c->d_fAL; f.J = c->d_fJ; f.Joff = c->d_fJoff;
   f.jval = c->d_fjval; f.jrow = c->d_fjrow; f.njval = (int)c->tables.Jval.size();
-  f.center = c->d_fcen; f.radius = c->d_frad; f.kR = c->d_fkR; f.iR = c->d_fiR;
+  f.center = c->d_fcen; f.radius = c->d_frad; f.kR = c->d_fkR; f.kRi = c->d_fkRi; f.iR = c->d_fiR;
+  f.kinv = c->kappa > 0 ? 1.0 / c->kappa : 0.0;
   return f;
 }
 // flops of one translation at order p: four rotations by J, the z-translation sum
@@ -608,65 +622,118 @@ inline double flops_translation(int p) {
   return 8.0 * rot + oz;
 }
 // flops of one multipole-to-local translation as k_fmm_m2l_fast performs it: four sparse
-// rotations by J, four z-rotations, the z translation per (l_out, |m|, l_in)
+// rotations by J, four z-rotations, the degree scalings of input and output and the z
+// translation per (l_out, |m|, l_in)
 inline double flops_m2l_fast(int kernel, int p, size_t njval) {
   double oz = 0.0;
   for (int lo = 0; lo <= p; ++lo)
     for (int am = 0; am <= lo; ++am)
       for (int li = am; li <= p; ++li) {
         const int nk = std::min(lo, li) - am + 1;
-        oz += (kernel == 0 ? 3.0 * nk + 3.0 : 2.0) + (am ? 4.0 : 2.0);
+        oz += (kernel == 0 ? 2.0 * nk : 0.0) + (am ? 4.0 : 2.0);
       }
-  return 2.0 * 2.0 * (double)njval + 4.0 * 6.0 * p * (p + 1) / 2.0 + oz;
+  const double P = (p + 1.0) * (p + 1.0);
+  return 2.0 * 2.0 * (double)njval + 4.0 * 6.0 * p * (p + 1) / 2.0 + 2.0 * P + oz;
 }
-// LDS configuration of k_fmm_m2l_fast: wavefronts per block and whether the
-// coefficient tables fit in LDS next to the rotation rows (0 waves: not usable)
-void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes) {
-  int dev = 0, maxlds = 0, cu_lds = 0;
+template <int NI>
+const void* m2l_fast_fn(bool alds) {
+  return alds ? reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, true>)
+              : reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, false>);
+}
+const void* m2l_fast_fn(int NI, bool alds) {
+  switch (NI) {
+    case 1: return m2l_fast_fn<1>(alds);
+    case 2: return m2l_fast_fn<2>(alds);
+    case 3: return m2l_fast_fn<3>(alds);
+    case 4: return m2l_fast_fn<4>(alds);
+    default: return m2l_fast_fn<5>(alds);
+  }
+}
+// Block layout of k_fmm_m2l_fast: the most resident wavefronts per compute unit as
+// reported by the occupancy calculator (registers and LDS); ties go to the tables in
+// LDS, then to larger blocks.  nw = 0: no layout fits.
+void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes, int& blocks_per_cu) {
+  auto& cc = c->m2l_cfg[kernel];
+  if (cc.valid) {
+    nw = cc.nw; alds = cc.alds; bytes = cc.bytes; blocks_per_cu = cc.per_cu;
+    return;
+  }
+  int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  HIPCHK(hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
-  cu_lds = std::max(cu_lds, maxlds);
-  const int p = c->fmm_order;
-  const int nA = (int)c->tables.Ap.size(), nj = (int)c->tables.Jval.size();
-  // most resident wavefronts per compute unit (at most 32); ties go to the tables in
-  // LDS, then to larger blocks
+  const int p = c->fmm_order, P = (p + 1) * (p + 1), NI = (P + 63) / 64;
+  const auto& tb = c->tables;
+  const int nZ = (int)tb.Z[kernel][0].size(), nj = (int)tb.Jval.size();
   nw = 0;
   alds = false;
   bytes = 0;
+  blocks_per_cu = 0;
+  if (NI > 5) return;
   int best = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool a = pass == 0;
+    const void* fn = m2l_fast_fn(NI, a);
     for (int w : {16, 8, 4, 2, 1}) {
       if (c->m2l_waves > 0 && w != c->m2l_waves) continue;
-      const size_t b = m2l_fast_lds_bytes(kernel, p, nA, nj, w, a);
+      const size_t b = m2l_fast_lds_bytes(p, nZ, nj, tb.nslot, w, a);
       if (b > (size_t)maxlds) continue;
-      const int blocks = std::min((int)((size_t)cu_lds / b), 32 / w);
-      const int waves = w * blocks;
-      if (waves > best) { best = waves; nw = w; alds = a; bytes = b; }
+      if (b > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b));
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * w, b) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      const int waves = w * nb;
+      if (waves > best) { best = waves; nw = w; alds = a; bytes = b; blocks_per_cu = nb; }
     }
   }
+  cc.valid = true; cc.nw = nw; cc.alds = alds; cc.bytes = bytes; cc.per_cu = blocks_per_cu;
+}
+template <int NI>
+void launch_m2l_fast(ddlpb_ctx* c, const FmmDev& f, const M2LTab& zt, int nw, bool alds, size_t bytes, int blocks,
+                     const int* lptr, const int* lidx, int transposed, const double* in, double* out) {
+  if (alds)
+    hipLaunchKernelGGL((k_fmm_m2l_fast<NI, true>), dim3(blocks), dim3(64 * nw), bytes, c->stream, f, zt,
+                       c->tree.nnodes, lptr, lidx, transposed, in, out);
+  else
+    hipLaunchKernelGGL((k_fmm_m2l_fast<NI, false>), dim3(blocks), dim3(64 * nw), bytes, c->stream, f, zt,
+                       c->tree.nnodes, lptr, lidx, transposed, in, out);
+}
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx, int transposed, const double* in,
                 double* out) {
   const auto& t = c->tree;
+  const auto& tb = c->tables;
   KScope ks(c, f.kernel == 0 ? (transposed ? "m2l_yukawa_T" : "m2l_yukawa") : (transposed ? "m2l_laplace_T" : "m2l_laplace"),
-            flops_m2l_fast(f.kernel, f.p, c->tables.Jval.size()) * (double)t.m2l_src.size());
-  int nw;
+            flops_m2l_fast(f.kernel, f.p, tb.Jval.size()) * (double)t.m2l_src.size());
+  int nw, per_cu;
   bool alds;
   size_t bytes;
-  m2l_config(c, f.kernel, nw, alds, bytes);
+  m2l_config(c, f.kernel, nw, alds, bytes, per_cu);
+  const int P = (f.p + 1) * (f.p + 1), NI = (P + 63) / 64;
   if (nw > 0) {
-    const void* fn = alds ? reinterpret_cast<const void*>(&k_fmm_m2l_fast<true>)
-                          : reinterpret_cast<const void*>(&k_fmm_m2l_fast<false>);
-    if (bytes > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    const int blocks = std::max(1, std::min((t.nnodes + nw - 1) / nw, 4096));
-    if (alds)
-      hipLaunchKernelGGL(k_fmm_m2l_fast<true>, dim3(blocks), dim3(64 * nw), bytes, c->stream, f, t.nnodes, lptr, lidx,
-                         transposed, in, out);
-    else
-      hipLaunchKernelGGL(k_fmm_m2l_fast<false>, dim3(blocks), dim3(64 * nw), bytes, c->stream, f, t.nnodes, lptr, lidx,
-                         transposed, in, out);
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    c->m2l_layout = nw * (alds ? 1 : -1);
+    const int blocks = std::max(1, std::min((t.nnodes + nw - 1) / nw, ncu * std::max(per_cu, 1)));
+    M2LTab zt;
+    zt.Z = c->d_fZ[f.kernel][transposed ? 1 : 0];
+    zt.slot = c->d_fZslot[f.kernel];
+    zt.order = transposed ? c->d_fm2ltord : c->d_fm2lord;
+    zt.counter = c->d_fctr;
+    zt.nZ = (int)tb.Z[f.kernel][0].size();
+    zt.nslot = tb.nslot;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 0);
+    switch (NI) {
+      case 1: launch_m2l_fast<1>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
+      case 2: launch_m2l_fast<2>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
+      case 3: launch_m2l_fast<3>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
+      case 4: launch_m2l_fast<4>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
+      default: launch_m2l_fast<5>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
+    }
   } else {
     hipLaunchKernelGGL(k_fmm_m2l, dim3(std::min(t.nnodes, 8192)), dim3(64), 0, c->stream, f, t.nnodes, lptr, lidx,
                        transposed, in, out);
@@ -1001,6 +1068,10 @@ void upload_and_init(ddlpb_ctx* c) {
     up(c->d_fJoff, c->tables.Joff.data(), c->tables.Joff.size() * sizeof(int));
     up(c->d_fjval, c->tables.Jval.data(), c->tables.Jval.size() * sizeof(double));
     up(c->d_fjrow, c->tables.Jrow.data(), c->tables.Jrow.size() * sizeof(int));
+    for (int k = 0; k < 2; ++k) {
+      for (int d = 0; d < 2; ++d) up(c->d_fZ[k][d], c->tables.Z[k][d].data(), c->tables.Z[k][d].size() * sizeof(double));
+      up(c->d_fZslot[k], c->tables.Zslot[k].data(), c->tables.Zslot[k].size() * sizeof(int));
+    }
     // sigma_l(kappa^2 r_i^2) up to degree p (normalisation of the sphere locals)
     std::vector<double> sgp((size_t)M * (p1 + 1)), sgt(p1 + 2), qs(M);
     for (int j = 0; j < M; ++j) {
@@ -1038,10 +1109,12 @@ void upload_tree(ddlpb_ctx* c) {
   up(c->d_fm2ls, t.m2l_src.data(), t.m2l_src.size() * sizeof(int));
   up(c->d_fm2ltp, t.m2lt_ptr.data(), t.m2lt_ptr.size() * sizeof(int));
   up(c->d_fm2ltt, t.m2lt_tgt.data(), t.m2lt_tgt.size() * sizeof(int));
+  up(c->d_fm2lord, t.m2l_order.data(), t.m2l_order.size() * sizeof(int));
+  up(c->d_fm2ltord, t.m2lt_order.data(), t.m2lt_order.size() * sizeof(int));
   up(c->d_fnp, t.near_ptr.data(), t.near_ptr.size() * sizeof(int));
   up(c->d_fni, t.near_idx.data(), t.near_idx.size() * sizeof(int));
   hipLaunchKernelGGL(k_fmm_node_radial, dim3(nblk(t.nnodes, 128)), dim3(128), 0, c->stream, t.nnodes, c->fmm_order,
-                     c->kappa, c->d_frad, c->d_fkR, c->d_fiR);
+                     c->kappa, c->d_frad, c->d_fkR, c->d_fkRi, c->d_fiR);
   HIPCHK(hipGetLastError());
   c->stats.n_m2l = (int64_t)t.m2l_src.size();
   c->stats.n_near_pairs = (int64_t)t.near_idx.size();
@@ -1405,6 +1478,7 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "m2l_waves") {
     if (!(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
+    c->m2l_cfg[0].valid = c->m2l_cfg[1].valid = false;
   } else if (k == "theta") {
     if (fixed) return DDLPB_ESTATE;
     if (!(v > 0 && v < 1)) return DDLPB_EINVAL;

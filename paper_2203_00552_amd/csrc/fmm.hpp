@@ -37,7 +37,9 @@ struct FmmDev {
   const double* center;  // [nn][3]
   const double* radius;  // [nn]
   const double* kR;      // [nn][P1]: k_l(kappa R_node)
+  const double* kRi;     // [nn][P1]: 1 / k_l(kappa R_node)
   const double* iR;      // [nn][P1]: i_l(kappa R_node)
+  double kinv;           // 1 / kappa
 };
 
 struct TransScratch {
@@ -239,7 +241,7 @@ __device__ __forceinline__ const double* coef_table(const FmmDev& f, int kind) {
 
 // per-node Bessel scales k_l(kappa R), i_l(kappa R), l = 0..p
 __global__ void k_fmm_node_radial(int nn, int p, double kappa, const double* __restrict__ radius, double* __restrict__ kR,
-                                  double* __restrict__ iR) {
+                                  double* __restrict__ kRi, double* __restrict__ iR) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const double z = kappa * radius[n];
@@ -249,6 +251,7 @@ __global__ void k_fmm_node_radial(int nn, int p, double kappa, const double* __r
   double zl = 1.0;
   for (int l = 0; l <= p; ++l) {
     kR[n * (p + 1) + l] = kk[l];
+    kRi[n * (p + 1) + l] = 1.0 / kk[l];
     iR[n * (p + 1) + l] = sg[l] * zl;
     zl *= z;
   }
@@ -318,16 +321,21 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __r
 }
 
 // ---------------------------------------------------------------------------
-// Multipole-to-local, one wavefront per translation, every table in LDS.
+// Multipole-to-local, one wavefront per translation, tables in LDS.
 //
 // Same operator as translate(kind 1) with the work laid out for a wavefront:
 //   * the rotation angles enter only through cos/sin of m*phi and m*theta, taken as
 //     integer powers of the unit complex numbers built from the centre offset
 //     (no trigonometric calls);
 //   * J and J^T are applied through their sparse rows (a quarter of the entries);
-//   * the z translation is computed once per (l_out, |m|) and applied to +m and -m;
+//   * the z translation is computed once per (l_out, |m|) pair and applied to +m and
+//     -m, with each lane reading its coefficients contiguously and the pairs dealt
+//     to lanes by longest-first balancing;
 //   * the first rotation is fused with the load of the input expansion and the last
-//     one with the accumulation.
+//     one with the accumulation, which stays in registers; the next source of the
+//     list is fetched into registers while the current one is translated;
+//   * wavefronts take target nodes from a counter in the order given by `order`
+//     (longest lists first).
 // LDS: the tables (shared by the block) followed by one scratch area per wavefront.
 __device__ __forceinline__ double ipow_d(double b, int e) {
   double r = 1.0;
@@ -351,148 +359,205 @@ __device__ __forceinline__ void cpow_d(double c, double s, int e, double& rc, do
   rs = xs;
 }
 
-__host__ __device__ constexpr int m2l_fast_wave_doubles(int p) { return 3 * (p + 1) * (p + 1) + 12 * (p + 1); }
+__host__ __device__ constexpr int m2l_fast_wave_doubles(int p) { return 2 * (p + 1) * (p + 1) + 8 * (p + 1); }
 
 // J (mat 0) or J^T (mat 1) applied to src, written to dst (degree p)
 __device__ __forceinline__ void japply_sparse(const double* __restrict__ jv, const int* __restrict__ jr, int mat, int P,
                                               const double* src, double* dst, int lane) {
   for (int t = lane; t < P; t += 64) {
     const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
-    const int l = (int)sqrtf((float)t + 0.5f);
-    const int c0 = d & 255, cnt = (d >> 8) & 255, st = d >> 16;
-    const double* x = src + l * l + c0;
+    const int cnt = (d >> 12) & 255, st = d >> 20;
+    const double* x = src + (d & 4095);
+    const double* v = jv + off;
     double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += jv[off + k] * x[st * k];
+    for (int k = 0; k < cnt; ++k) s += v[k] * x[st * k];
     dst[t] = s;
   }
 }
+// order m of the lane's item i, packed 6 bits per item (offset 32)
+__device__ __forceinline__ int item_m(int mpack, int i) { return ((mpack >> (6 * i)) & 63) - 32; }
+__device__ __forceinline__ int item_l(int lpack, int i) { return (lpack >> (6 * i)) & 63; }
 
-template <bool ALDS>
-__global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, int nn, const int* __restrict__ lptr,
+// in-place rotation about z by the angle with cos/sin of m*angle = ((-1)^m c[m], ss (-1)^m s[m])
+// (pairs (l, +-m) handled by the lane of the +m entry)
+template <int NI>
+__device__ __forceinline__ void zrot_alt(double* b, int P, const double* c, const double* s, double ss, int lane,
+                                         int mpack) {
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int t = lane + 64 * i, m = item_m(mpack, i);
+    if (t < P && m > 0) {
+      const double sg = (m & 1) ? -1.0 : 1.0;
+      const double a = b[t], bb = b[t - 2 * m], co = sg * c[m], si = ss * sg * s[m];
+      b[t] = a * co - bb * si;
+      b[t - 2 * m] = a * si + bb * co;
+    }
+  }
+}
+
+// z-translation table of one M2L launch (kernel type and direction)
+struct M2LTab {
+  const double* Z;  // entries, see the host tables
+  const int* slot;  // [nslot][2]: lo << 8 | |m| (or -1), offset
+  const int* order; // target node order (longest lists first)
+  int* counter;     // work counter, zero at launch
+  int nZ, nslot;
+};
+
+template <int NI, bool ALDS>
+__global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int nn, const int* __restrict__ lptr,
                                                        const int* __restrict__ lidx, int transposed,
                                                        const double* __restrict__ Ein, double* __restrict__ Eout) {
   extern __shared__ double smem[];
   const int p = f.p, P1 = p + 1, P = P1 * P1;
   const int nw = blockDim.x >> 6;
-  const int nat = f.kernel == 0 ? f.nA : P1 * P1 * P1;
-  const int naoff = (ALDS && f.kernel == 0) ? P1 * P1 * P1 : 0;
+  const bool yuk = f.kernel == 0;
   // block-shared tables
   double* jv = smem;
-  double* at = jv + f.njval;
-  double* wsb = at + (ALDS ? nat : 0);
+  double* zl = jv + f.njval;
+  double* wsb = zl + (ALDS ? zt.nZ : 0);
   int* jr = (int*)(wsb + nw * m2l_fast_wave_doubles(p));
-  int* ao = jr + 4 * P;
-  const double* gt = coef_table(f, 1);
+  int* zs = jr + 4 * P;
   for (int t = threadIdx.x; t < f.njval; t += blockDim.x) jv[t] = f.jval[t];
   for (int t = threadIdx.x; t < 4 * P; t += blockDim.x) jr[t] = f.jrow[t];
+  for (int t = threadIdx.x; t < 2 * zt.nslot; t += blockDim.x) zs[t] = zt.slot[t];
   if constexpr (ALDS) {
-    for (int t = threadIdx.x; t < nat; t += blockDim.x) at[t] = gt[t];
-    for (int t = threadIdx.x; t < naoff; t += blockDim.x) ao[t] = f.Aoff[t];
+    for (int t = threadIdx.x; t < zt.nZ; t += blockDim.x) zl[t] = zt.Z[t];
   }
   __syncthreads();
-  const double* A;
-  const int* AO;
-  if constexpr (ALDS) { A = at; AO = ao; } else { A = gt; AO = f.Aoff; }
+  const double* Z;
+  if constexpr (ALDS) Z = zl; else Z = zt.Z;
 
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform: keep it (and every scratch address) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   double* b0 = wsb + w * m2l_fast_wave_doubles(p);
   double* b1 = b0 + P;
-  double* acc = b1 + P;
-  double* bes = acc + P;       // 2p+2
-  double* pw1 = bes + 2 * P1;  // 2p+2
-  double* pw2 = pw1 + 2 * P1;  // 2p+2
-  double* radS = pw2 + 2 * P1;
-  double* radT = radS + P1;
-  double* cph = radT + P1;
+  double* kt = b1 + P;         // k_n(z) z^n, n = 0..2p (2p+2)
+  double* sIn = kt + 2 * P1;   // degree scale of the input
+  double* sOut = sIn + P1;     // degree scale of the output
+  double* cph = sOut + P1;
   double* sph = cph + P1;
   double* cth = sph + P1;
   double* sth = cth + P1;
-  const int npair = P1 * (P1 + 1) / 2;
 
-  for (int n = blockIdx.x * nw + w; n < nn; n += gridDim.x * nw) {
-    for (int t = lane; t < P; t += 64) acc[t] = 0.0;
-    for (int q = lptr[n]; q < lptr[n + 1]; ++q) {
+  // lane items t = lane + 64 i: degree and order, 6 bits each
+  int mpack = 0, lpack = 0;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int t = lane + 64 * i;
+    const int l = (int)sqrtf((float)t + 0.5f);
+    mpack |= ((t - l * l - l + 32) & 63) << (6 * i);
+    lpack |= (l & 63) << (6 * i);
+  }
+
+  for (;;) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(zt.counter, 1);
+    k = __builtin_amdgcn_readfirstlane(__shfl(k, 0));
+    if (k >= nn) break;
+    const int n = zt.order[k];
+    const int q0 = lptr[n], q1 = lptr[n + 1];
+    double acc[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) acc[i] = 0.0;
+    // data of the fixed node n (target, or source when transposed): i_l(kappa R) or 1/k_l(kappa R)
+    const double cnx = f.center[3 * n], cny = f.center[3 * n + 1], cnz = f.center[3 * n + 2];
+    double rfix = 0.0;
+    if (yuk && lane <= p) rfix = transposed ? f.kRi[n * P1 + lane] : f.iR[n * P1 + lane];
+    // first source, fetched ahead
+    double va[NI], vb[NI], vc = 0.0, vr = 0.0;
+    auto fetch = [&](int o) {
+      const double* src = Ein + (long)o * P;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int t = lane + 64 * i;
+        va[i] = t < P ? src[t] : 0.0;
+        vb[i] = t < P ? src[t - 2 * item_m(mpack, i)] : 0.0;
+      }
+      vc = lane < 3 ? f.center[3 * o + lane] : 0.0;
+      vr = 0.0;
+      if (yuk && lane <= p) vr = transposed ? f.iR[o * P1 + lane] : f.kRi[o * P1 + lane];
+    };
+    if (q0 < q1) fetch(lidx[q0]);
+    for (int q = q0; q < q1; ++q) {
+      const double cox = __shfl(vc, 0), coy = __shfl(vc, 1), coz = __shfl(vc, 2);
+      const double rvar = vr;
       const int o = lidx[q];
-      const int S = transposed ? n : o, T = transposed ? o : n;
-      const double dx = f.center[3 * T] - f.center[3 * S], dy = f.center[3 * T + 1] - f.center[3 * S + 1],
-                   dz = f.center[3 * T + 2] - f.center[3 * S + 2];
+      const double dx = transposed ? cox - cnx : cnx - cox, dy = transposed ? coy - cny : cny - coy,
+                   dz = transposed ? coz - cnz : cnz - coz;
       const double rxy = sqrt(dx * dx + dy * dy), rho = sqrt(dx * dx + dy * dy + dz * dz);
-      tsync<true>();  // previous translation done with the per-translation tables
+      const double irho = 1.0 / rho;
+      tsync<true>();  // the previous translation is done with the per-translation tables
       if (lane <= p) {
         double c1 = 1.0, s1 = 0.0;
-        if (rxy > 0.0) { c1 = dx / rxy; s1 = dy / rxy; }
+        if (rxy > 0.0) { const double ir = 1.0 / rxy; c1 = dx * ir; s1 = dy * ir; }
         cpow_d(c1, s1, lane, cph[lane], sph[lane]);
-        cpow_d(dz / rho, rxy / rho, lane, cth[lane], sth[lane]);
-        if (f.kernel == 0) {
-          radS[lane] = 1.0 / f.kR[S * P1 + lane];
-          radT[lane] = f.iR[T * P1 + lane];
+        cpow_d(dz * irho, rxy * irho, lane, cth[lane], sth[lane]);
+        double u, v;  // source-degree and target-degree scales
+        if (yuk) {
+          // k-sum against k_n(z) z^n; z^-(l+l') (-1)^l and the node scales go to the degrees
+          const double zi = irho * f.kinv;
+          const double zl = ipow_d(zi, lane);
+          const double rs = transposed ? rfix : rvar, rt = transposed ? rvar : rfix;
+          u = rs * zl * ((lane & 1) ? -1.0 : 1.0);
+          v = rt * zl;
+        } else {
+          const double RT = f.radius[transposed ? o : n], RS = f.radius[transposed ? n : o];
+          u = ipow_d(RS * irho, lane + 1);
+          v = ipow_d(RT * irho, lane);
         }
+        sIn[lane] = transposed ? v : u;
+        sOut[lane] = transposed ? u : v;
       }
-      if (f.kernel == 0) {
-        const double z = f.kappa * rho;
-        if (lane <= 2 * p) {
-          // k_n(z) = (pi/2) e^-z / z sum_j (n+j)! / (j! (n-j)!) (2z)^-j
-          const int nb = lane;
-          const double h = 0.5 / z;
-          double term = 1.0, sum = 1.0;
-          for (int j = 0; j < nb; ++j) {
-            term *= (double)(nb + j + 1) * (double)(nb - j) / (double)(j + 1) * h;
-            sum += term;
-          }
-          bes[lane] = 1.5707963267948966 * exp(-z) / z * sum;
-          pw1[lane] = ipow_d(-1.0 / z, lane);
+      if (yuk && lane <= 2 * p) {
+        // k_n(z) z^n by the upward recurrence kt_{n+1} = z^2 kt_{n-1} + (2n+1) kt_n
+        const double z = f.kappa * rho, z2 = z * z;
+        double km = 1.5707963267948966 * exp(-z) * irho * f.kinv;
+        double kc = km * (z + 1.0);
+        for (int j = 1; j < lane; ++j) {
+          const double kn = z2 * km + (2.0 * j + 1.0) * kc;
+          km = kc;
+          kc = kn;
         }
-      } else if (lane <= p + 1) {
-        pw1[lane] = ipow_d(f.radius[T] / rho, lane);
-        pw2[lane] = ipow_d(f.radius[S] / rho, lane);
+        kt[lane] = lane == 0 ? km : kc;
       }
       tsync<true>();
-      // input, rotated by -phi about z
-      const double* src = Ein + (long)o * P;
-      for (int t = lane; t < P; t += 64) {
-        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
-        if (m == 0) b0[t] = src[t];
-        else if (m > 0) {
-          const double a = src[t], b = src[t - 2 * m], co = cph[m], si = -sph[m];
-          b0[t] = a * co - b * si;
-          b0[t - 2 * m] = a * si + b * co;
-        }
+      // input scaled by degree and rotated by -phi about z; then the next source is
+      // fetched into the same registers
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        if (lane + 64 * i >= P) continue;
+        const int m = item_m(mpack, i), am = m < 0 ? -m : m;
+        double v = va[i];
+        if (m > 0) v = va[i] * cph[am] + vb[i] * sph[am];
+        else if (m < 0) v = va[i] * cph[am] - vb[i] * sph[am];
+        b0[lane + 64 * i] = v * sIn[item_l(lpack, i)];
       }
+      if (q + 1 < q1) fetch(lidx[q + 1]);
       tsync<true>();
       japply_sparse(jv, jr, 0, P, b0, b1, lane);
       tsync<true>();
-      // rotation by pi - theta: cos = (-1)^m cos(m theta), sin = -(-1)^m sin(m theta)
-      for (int t = lane; t < P; t += 64) {
-        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
-        if (m > 0) {
-          const double sg = (m & 1) ? -1.0 : 1.0;
-          const double a = b1[t], b = b1[t - 2 * m], co = sg * cth[m], si = -sg * sth[m];
-          b1[t] = a * co - b * si;
-          b1[t - 2 * m] = a * si + b * co;
-        }
-      }
+      zrot_alt<NI>(b1, P, cth, sth, -1.0, lane, mpack);  // pi - theta
       tsync<true>();
       japply_sparse(jv, jr, 1, P, b1, b0, lane);
       tsync<true>();
-      // translation along z: one (l_out, |m|) pair per lane, applied to +m and -m
-      for (int u = lane; u < npair; u += 64) {
-        int lo = (int)((sqrtf(8.0f * u + 1.0f) - 1.0f) * 0.5f);
-        while (lo * (lo + 1) / 2 > u) --lo;
-        while ((lo + 1) * (lo + 2) / 2 <= u) ++lo;
-        const int am = u - lo * (lo + 1) / 2;
+      // translation along z
+      for (int s = lane; s < zt.nslot; s += 64) {
+        const int code = zs[2 * s];
+        if (code < 0) continue;
+        const int lo = code >> 8, am = code & 255;
+        const double* zp = Z + zs[2 * s + 1];
         double sp = 0.0, sm = 0.0;
         for (int li = am; li <= p; ++li) {
-          const int l = transposed ? lo : li, lp = transposed ? li : lo;
           double e;
-          if (f.kernel == 0) {
-            const double* Ar = A + AO[(l * P1 + lp) * P1 + am] - am;
-            const int kmax = min(l, lp);
-            double sk = 0.0;
-            for (int k = am; k <= kmax; ++k) sk += Ar[k] * bes[l + lp - k] * pw1[k];
-            e = sk * radT[lp] * radS[l];
-            if (l & 1) e = -e;
+          if (yuk) {
+            const int nk = min(lo, li) - am + 1;
+            const double* kp = kt + lo + li - am;
+            e = 0.0;
+            for (int kk = 0; kk < nk; ++kk) e += zp[kk] * kp[-kk];
+            zp += nk;
           } else {
-            e = A[(l * P1 + lp) * P1 + am] * pw1[lp] * pw2[l + 1];
+            e = *zp++;
           }
           sp += e * b0[li * li + li + am];
           sm += e * b0[li * li + li - am];
@@ -503,41 +568,35 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, int nn, const i
       tsync<true>();
       japply_sparse(jv, jr, 0, P, b1, b0, lane);
       tsync<true>();
-      // rotation by theta - pi: cos = (-1)^m cos(m theta), sin = (-1)^m sin(m theta)
-      for (int t = lane; t < P; t += 64) {
-        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
-        if (m > 0) {
-          const double sg = (m & 1) ? -1.0 : 1.0;
-          const double a = b0[t], b = b0[t - 2 * m], co = sg * cth[m], si = sg * sth[m];
-          b0[t] = a * co - b * si;
-          b0[t - 2 * m] = a * si + b * co;
-        }
-      }
+      zrot_alt<NI>(b0, P, cth, sth, 1.0, lane, mpack);  // theta - pi
       tsync<true>();
       japply_sparse(jv, jr, 1, P, b0, b1, lane);
       tsync<true>();
-      // rotation by phi, accumulated
-      for (int t = lane; t < P; t += 64) {
-        const int l = (int)sqrtf((float)t + 0.5f), m = t - l * l - l;
-        if (m == 0) acc[t] += b1[t];
-        else if (m > 0) {
-          const double a = b1[t], b = b1[t - 2 * m], co = cph[m], si = sph[m];
-          acc[t] += a * co - b * si;
-          acc[t - 2 * m] += a * si + b * co;
+      // rotation by phi, scaled by degree, accumulated in registers
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        if (lane + 64 * i >= P) continue;
+        const int m = item_m(mpack, i), am = m < 0 ? -m : m;
+        const double a = b1[lane + 64 * i];
+        double r = a;
+        if (m != 0) {
+          const double bm = b1[lane + 64 * i - 2 * m];
+          r = m > 0 ? a * cph[am] - bm * sph[am] : bm * sph[am] + a * cph[am];
         }
+        acc[i] += r * sOut[item_l(lpack, i)];
       }
     }
-    tsync<true>();
-    for (int t = lane; t < P; t += 64) Eout[(long)n * P + t] = acc[t];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      if (lane + 64 * i < P) Eout[(long)n * P + lane + 64 * i] = acc[i];
   }
 }
 
 // LDS bytes of k_fmm_m2l_fast for nw wavefronts per block
-inline size_t m2l_fast_lds_bytes(int kernel, int p, int nA, int njval, int nw, bool alds) {
+inline size_t m2l_fast_lds_bytes(int p, int nZ, int njval, int nslot, int nw, bool alds) {
   const size_t P1 = p + 1, P = P1 * P1;
-  const size_t nat = kernel == 0 ? (size_t)nA : P1 * P1 * P1;
-  size_t d = (size_t)njval + (alds ? nat : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
-  size_t i = 4 * P + ((alds && kernel == 0) ? P1 * P1 * P1 : 0);
+  const size_t d = (size_t)njval + (alds ? (size_t)nZ : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
+  const size_t i = 4 * P + 2 * (size_t)nslot;
   return d * sizeof(double) + i * sizeof(int);
 }
 

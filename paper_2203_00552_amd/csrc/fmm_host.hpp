@@ -34,6 +34,7 @@ struct Tree {
   std::vector<int> m2l_ptr, m2l_src;  // per target node, source nodes (sorted)
   std::vector<int> m2lt_ptr, m2lt_tgt;  // transposed: per source node, target nodes
   std::vector<int> near_ptr, near_idx;  // per target sphere, source spheres (self included)
+  std::vector<int> m2l_order, m2lt_order;  // nodes by decreasing list length (work order)
 };
 
 inline void build_tree(int M, const double* x, const double* r, Tree& t) {
@@ -138,6 +139,14 @@ inline void build_lists(int M, const double* r, double theta, Tree& t) {
     t.m2lt_tgt.insert(t.m2lt_tgt.end(), m2lt[n].begin(), m2lt[n].end());
     t.m2lt_ptr[n + 1] = (int)t.m2lt_tgt.size();
   }
+  auto by_length = [&](const std::vector<int>& ptr, std::vector<int>& ord) {
+    ord.resize(t.nnodes);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+  };
+  by_length(t.m2l_ptr, t.m2l_order);
+  by_length(t.m2lt_ptr, t.m2lt_order);
   t.near_ptr.assign(M + 1, 0);
   t.near_idx.clear();
   for (int i = 0; i < M; ++i) {
@@ -182,10 +191,20 @@ struct Tables {
   std::vector<int> Joff;
   // Sparse rows of J (mat 0) and J^T (mat 1).  Every row of a block has its nonzeros
   // on every second column of one run (the blocks split by the parity classes of m):
-  // Jrow[2 * (mat * L + t)] = offset into Jval, Jrow[2 * (mat * L + t) + 1] =
-  // first column (m + l) | count << 8 | column step << 16, row t = l^2 + l + m'.
+  // Jrow[2 * (mat * L + t)] = offset into Jval, Jrow[2 * (mat * L + t) + 1] = index
+  // l^2 + (first m + l) of the first column | count << 12 | column step << 20, for
+  // the row t = l^2 + l + m'.
   std::vector<double> Jval;
   std::vector<int> Jrow;
+  // z-translation coefficients of the M2L kernel laid out per output pair (lo, |m|):
+  // Z[kern][dir] holds for every pair the entries of l_in = |m|..p in order (Yukawa:
+  // k = |m|..min(lo, l_in); Laplace: one value); dir 0 is the forward translation
+  // (lo = target degree), dir 1 its transpose (lo = source degree).  Pairs are dealt
+  // to the 64 lanes by longest-first balancing: Zslot[kern][2 s] = lo << 8 | |m| of
+  // the pair in slot s (lane s mod 64; -1 when empty), Zslot[kern][2 s + 1] = offset.
+  std::vector<double> Z[2][2];
+  std::vector<int> Zslot[2];
+  int nslot = 0;
 };
 
 inline void build_tables(int pmax, Tables& tb) {
@@ -219,6 +238,52 @@ inline void build_tables(int pmax, Tables& tb) {
         tb.Aoff[((size_t)l * P1 + lp) * P1 + am] = (int)tb.Ap.size();
         for (int k = am; k <= std::min(l, lp); ++k) tb.Ap.push_back(tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k]);
       }
+  {
+    const int npair = P1 * (P1 + 1) / 2;
+    tb.nslot = 64 * ((npair + 63) / 64);
+    const int R = tb.nslot / 64;
+    for (int kern = 0; kern < 2; ++kern) {
+      std::vector<int> off(npair);
+      std::vector<double> work(npair);
+      for (int d = 0; d < 2; ++d) tb.Z[kern][d].clear();
+      for (int lo = 0; lo <= pmax; ++lo)
+        for (int am = 0; am <= lo; ++am) {
+          const int u = lo * (lo + 1) / 2 + am;
+          off[u] = (int)tb.Z[kern][0].size();
+          work[u] = 0.0;
+          for (int li = am; li <= pmax; ++li) {
+            const int kmax = std::min(lo, li);
+            for (int d = 0; d < 2; ++d) {
+              const int l = d ? lo : li, lp = d ? li : lo;
+              if (kern == 0) {  // (-1)^k folded in: the kernel sums against k_n(z) z^n
+                for (int k = am; k <= kmax; ++k)
+                  tb.Z[kern][d].push_back(tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k] * ((k & 1) ? -1.0 : 1.0));
+              } else {
+                tb.Z[kern][d].push_back(tb.AL[1 * (size_t)P1 * P1 * P1 + ((size_t)l * P1 + lp) * P1 + am]);
+              }
+            }
+            work[u] += kern == 0 ? 3.0 * (kmax - am + 1) + 7.0 : 7.0;
+          }
+        }
+      std::vector<int> order(npair);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+      std::vector<double> load(64, 0.0);
+      std::vector<int> used(64, 0);
+      tb.Zslot[kern].assign(2 * (size_t)tb.nslot, -1);
+      for (int u : order) {
+        int best = -1;
+        for (int ln = 0; ln < 64; ++ln)
+          if (used[ln] < R && (best < 0 || load[ln] < load[best])) best = ln;
+        const int slot = best + 64 * used[best]++;
+        load[best] += work[u];
+        int lo = 0;
+        while ((lo + 1) * (lo + 2) / 2 <= u) ++lo;
+        tb.Zslot[kern][2 * slot] = (lo << 8) | (u - lo * (lo + 1) / 2);
+        tb.Zslot[kern][2 * slot + 1] = off[u];
+      }
+    }
+  }
   // J_l[m', m] = sum_n w_n Y_lm'(s_n) Y_lm(Q^T s_n), Q = rotation by +90 degrees about x,
   // exact for a Lebedev rule of degree >= 2 pmax.
   const auto* rule = host::lebedev_rule_min_degree(2 * pmax);
@@ -262,7 +327,7 @@ inline void build_tables(int pmax, Tables& tb) {
         for (int b = first; b <= last; b += step) cols.push_back(b);
         const size_t t = (size_t)l * l + a;
         tb.Jrow[2 * (mat * L + t)] = (int)tb.Jval.size();
-        tb.Jrow[2 * (mat * L + t) + 1] = cols[0] | ((int)cols.size() << 8) | (step << 16);
+        tb.Jrow[2 * (mat * L + t) + 1] = (l * l + cols[0]) | ((int)cols.size() << 12) | (step << 20);
         for (int b : cols) tb.Jval.push_back(mat == 0 ? tb.J[tb.Joff[l] + a * w + b] : tb.J[tb.Joff[l] + b * w + a]);
       }
     }
