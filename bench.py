@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-atoms", type=int, default=60)
+    p.add_argument("--serve-requests", type=int, default=64,
+                   help="requests of the serving run (0: skip); the full workload has 512")
+    p.add_argument("--serve-slots", type=int, default=4)
     return p.parse_args()
 
 
@@ -58,6 +61,27 @@ def cpu_baseline(args):
             "sample": f"{n}-atom cluster of the same generator, lmax {args.lmax}, {args.nleb} points, "
                       f"tol {args.tol:g}, full energy+forces in {dt:.1f} s (direct O(M^2) sums: the "
                       f"oracle's cost per atom grows linearly with M)"}
+
+
+def serving(args):
+    """Continuous-batching run: Poisson arrivals (mean 200/s), atom counts log-uniform in
+    [50, 20000], lmax in {6, 8}, 110 or 302 points, tol 1e-6, energy + forces."""
+    from paper_2203_00552_amd import inputs
+    from paper_2203_00552_amd.serve import Request, Server, latency_summary, run_arrivals
+    spec = inputs.serving_requests(args.serve_requests, rate=200.0, seed=args.seed)
+    reqs, times = [], []
+    for k, sp in enumerate(spec):
+        x, r, q = inputs.lattice_cluster(sp["n"], seed=sp["seed"])
+        reqs.append(Request(x, r, q, lmax=sp["lmax"], n_lebedev=sp["n_lebedev"], tol=1e-6,
+                            precision=1 if args.precision == "mixed" else 0, rid=k))
+        times.append(sp["t"])
+    server = Server(slots=args.serve_slots)
+    res, span = run_arrivals(server, reqs, times)
+    server.close()
+    out = latency_summary(res, span)
+    out.update({"slots": args.serve_slots, "max_in_flight": server.max_in_flight, "rate_per_s": 200.0,
+                "precision": args.precision, "sizes": "log-uniform [50, 20000] atoms"})
+    return out
 
 
 def main():
@@ -126,6 +150,11 @@ def main():
         "phase_ms": {k: st[k] for k in ("ms_rhs", "ms_primal", "ms_adjoint", "ms_forces")},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])},
     }
+    ctx.close()
+    if args.serve_requests > 0:
+        log(f"serving run: {args.serve_requests} requests")
+        out["serving"] = serving(args)
+        log("serving run done")
     if not args.no_cpu_baseline:
         log("oracle sample on the host")
         out["cpu_baseline"] = cpu_baseline(args)

@@ -51,6 +51,10 @@ void ensure_constants() {
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_pmm), pmm.data(), pmm.size() * sizeof(double)));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_ra), ra.data(), ra.size() * sizeof(double)));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_rb), rb.data(), rb.size() * sizeof(double)));
+  std::vector<double> sinv((kLmaxDev + 2) * kSigTerms);
+  for (int l = 0; l <= kLmaxDev + 1; ++l)
+    for (int k = 0; k < kSigTerms; ++k) sinv[l * kSigTerms + k] = 0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_sinv), sinv.data(), sinv.size() * sizeof(double)));
   g_const_done[dev] = true;
 }
 
@@ -88,7 +92,7 @@ struct ddlpb_ctx {
   int *d_nptr = nullptr, *d_nidx = nullptr, *d_nrev = nullptr;
   double *d_f = nullptr, *d_U = nullptr;
   int *d_actcnt = nullptr, *d_actptr = nullptr, *d_actsph = nullptr, *d_actn = nullptr;
-  double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_ur = nullptr, *d_kr = nullptr;
+  double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_kr = nullptr;
   double *d_dtab = nullptr;
   double *d_m = nullptr, *d_lam = nullptr;
   double *d_psi = nullptr, *d_e = nullptr, *d_Phi = nullptr, *d_h = nullptr, *d_zr = nullptr, *d_ze = nullptr,
@@ -300,6 +304,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_yce = cv.take<double>(M * c->LUR);
   c->d_Cl = cv.take<double>(M * c->LUR);
   c->d_sgr = cv.take<double>(M * c->LUR);
+  c->d_isgr = cv.take<double>(M * c->LUR);
   c->d_ur = cv.take<double>(M * c->LUR);
   c->d_kr = cv.take<double>(M * c->LUR);
   c->d_dtab = cv.take<double>(3 * (size_t)c->L * c->LP);
@@ -535,10 +540,16 @@ void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, 
               const double* gr2, const double* ge, double cg, double* out) {
   KScope ks(c, "apply_LX", nearX ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
-    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LX_caps<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
-                                            c->LY, c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx,
-                                            c->d_cptr, c->d_capn, c->d_capslot, c->d_capw, c->d_pcp, c->d_U, c->d_sgr,
-                                            c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1, gr2, ge, cg, out));
+    LM_DISPATCH(c->lmax, {
+      const size_t lds = k_apply_LX_caps_lds_doubles<LMc>(c->N) * sizeof(double);
+      if (lds > 65536)
+        HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LX_caps<LMc>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL((k_apply_LX_caps<LMc>), dim3(c->M), dim3(256), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
+                         c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_cptr, c->d_capn, c->d_capslot,
+                         c->d_capw, c->d_pcp, c->d_U, c->d_isgr, c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1,
+                         gr2, ge, cg, out);
+    });
     HIPCHK(hipGetLastError());
     return;
   }
@@ -559,10 +570,16 @@ void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, co
                const double* lam, int llam, double* out) {
   KScope ks(c, "apply_LTZ", zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
-    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LTZ_caps<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
-                                            c->LY, c->d_Y, c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci,
-                                            c->d_rcn, c->d_rcw, c->d_U, c->d_sgr, c->d_ycr, c->d_yce, c->d_Cl, c->LUR,
-                                            c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam, out));
+    LM_DISPATCH(c->lmax, {
+      const size_t lds = k_apply_LTZ_caps_lds_doubles<LMc>(c->N) * sizeof(double);
+      if (lds > 65536)
+        HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LTZ_caps<LMc>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL((k_apply_LTZ_caps<LMc>), dim3(c->M), dim3(128), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
+                         c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw, c->d_U, c->d_isgr,
+                         c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam,
+                         out);
+    });
     HIPCHK(hipGetLastError());
     return;
   }
@@ -1056,6 +1073,9 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_yce, yce.data(), yce.size() * sizeof(double));
   up(c->d_Cl, Cl.data(), Cl.size() * sizeof(double));
   up(c->d_sgr, sgr.data(), sgr.size() * sizeof(double));
+  std::vector<double> isgr(sgr.size());
+  for (size_t k = 0; k < sgr.size(); ++k) isgr[k] = sgr[k] != 0.0 ? 1.0 / sgr[k] : 0.0;
+  up(c->d_isgr, isgr.data(), isgr.size() * sizeof(double));
   up(c->d_ur, ur.data(), ur.size() * sizeof(double));
   up(c->d_kr, kr.data(), kr.size() * sizeof(double));
   up(c->d_dtab, dtab.data(), dtab.size() * sizeof(double));
@@ -1144,7 +1164,15 @@ void geometry_on_device(ddlpb_ctx* c) {
   c->ncap = 0;
   for (int i = 0; i < M; ++i) c->ncap += cnt[i];
   c->stats.n_cap_pairs = c->ncap;
-  c->use_caps = (size_t)c->ncap <= c->cap_cap;
+  {
+    int dev = 0, maxlds = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    size_t need = 0;
+    LM_DISPATCH(c->lmax, need = std::max(k_apply_LX_caps_lds_doubles<LMc>(N), k_apply_LTZ_caps_lds_doubles<LMc>(N)) *
+                                sizeof(double));
+    c->use_caps = (size_t)c->ncap <= c->cap_cap && need <= (size_t)maxlds;
+  }
   if (c->use_caps) {
     std::vector<int> cp(M + 1, 0);
     for (int i = 0; i < M; ++i) cp[i + 1] = cp[i] + cnt[i];

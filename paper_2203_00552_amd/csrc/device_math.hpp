@@ -28,6 +28,9 @@ __host__ __device__ constexpr int lmi(int l, int m) { return l * l + l + m; }
 __constant__ double c_pmm[kLmaxDev + 1];
 __constant__ double c_ra[kTri];
 __constant__ double c_rb[kTri];
+// Coefficients of the sigma_l series: c_sinv[l * kSigTerms + k] = 1 / (2 (k+1) (2l+2k+3)).
+constexpr int kSigTerms = 64;
+__constant__ double c_sinv[(kLmaxDev + 2) * kSigTerms];
 
 // ------------------------------------------------------------------ dual
 template <class R>
@@ -98,6 +101,52 @@ __device__ __forceinline__ void for_each_solid_harmonic(const T& x, const T& y, 
   }
 }
 
+// The same harmonics split over four lanes: the lane with q = 0..3 produces the
+// columns m = q, q+4, q+8, ... (both signs), in increasing l; pmm/ra/rb are the
+// recurrence constants (copies of c_pmm/c_ra/c_rb, e.g. in LDS).
+template <int LM, class F>
+__device__ __forceinline__ void solid_harmonic_quad(double x, double y, double z, int q, const double* pmm,
+                                                    const double* ra, const double* rb, F&& f) {
+  constexpr int NC = LM / 4 + 1;
+  const double r2 = x * x + y * y + z * z;
+  double cq = 1.0, sq = 0.0;  // (x + i y)^q
+  for (int k = 0; k < q; ++k) {
+    const double c2 = x * cq - y * sq;
+    sq = x * sq + y * cq;
+    cq = c2;
+  }
+  const double c2 = x * x - y * y, s2 = 2.0 * x * y;
+  const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * c2 * s2;
+  double cm[NC], sm[NC], p1[NC], p2[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (k == 0) { cm[0] = cq; sm[0] = sq; }
+    else { cm[k] = cm[k - 1] * c4 - sm[k - 1] * s4; sm[k] = cm[k - 1] * s4 + sm[k - 1] * c4; }
+    p1[k] = 0.0;
+    p2[k] = 0.0;
+  }
+#pragma unroll
+  for (int l = 0; l <= LM; ++l) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int m = q + 4 * k;
+      if (m > l) continue;
+      double p;
+      if (m == l) p = pmm[m];
+      else if (m == l - 1) p = ra[tri(l, m)] * (z * p1[k]);
+      else p = ra[tri(l, m)] * (z * p1[k]) - rb[tri(l, m)] * (r2 * p2[k]);
+      p2[k] = p1[k];
+      p1[k] = p;
+      if (m == 0) {
+        f(l, l * l + l, p);
+      } else {
+        f(l, l * l + l + m, p * cm[k]);
+        f(l, l * l + l - m, p * sm[k]);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ Bessel weights
 // u_l = k_l(kappa rho) / rho^l for l = 0..LM (k_l = sqrt(pi/(2z)) K_{l+1/2}(z)).
 template <int LM, class T>
@@ -128,7 +177,9 @@ __device__ __forceinline__ void sigma_weights(const T& z2, int nterms, T* sg) {
     T term = T(R(1.0 / df));
     T sum = term;
     for (int k = 0; k < nterms; ++k) {
-      term = (term * z2) * R(0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0)));
+      const double ck = (l <= kLmaxDev + 1 && k < kSigTerms) ? c_sinv[l * kSigTerms + k]
+                                                             : 0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
+      term = (term * z2) * R(ck);
       sum = sum + term;
     }
     top[q] = sum;

@@ -727,11 +727,17 @@ __global__ void k_rcaps_fill(int M, int N, const double* __restrict__ xyz, const
 }
 
 // ------------------------------------------- apply L (near part) from cap lists
-// Same result as k_apply_LX: one block per sphere i; the coefficients of the
-// neighbours are staged in LDS, every thread evaluates whole caps, per-point sums
-// are taken in cap order (deterministic), then the An transforms.
+// Same result as k_apply_LX: one block per sphere i.  Each cap is evaluated by four
+// lanes (the harmonic columns m = q mod 4 of lane q, see solid_harmonic_quad) and
+// reduced across them; the coefficients of up to kNbrLds neighbours and the
+// recurrence constants are staged in LDS; per-point sums are taken in cap order
+// (deterministic), then the An transforms.  Dynamic LDS: k_apply_LX_caps_lds().
 constexpr int kCapChunk = 512;
 constexpr int kNbrLds = 16;
+template <int LM>
+__host__ __device__ constexpr size_t k_apply_LX_caps_lds_doubles(int N) {
+  return 4 * (size_t)N + 2 * kCapChunk + (size_t)kNbrLds * 2 * (LM + 1) * (LM + 1) + (LM + 1) + (LM + 1) * (LM + 2);
+}
 template <int LM>
 __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, const double* __restrict__ Y,
                                                         const double* __restrict__ leb, const double* __restrict__ xyz,
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
                                                         const int* __restrict__ nidx, const int* __restrict__ cptr,
                                                         const int* __restrict__ cap_n, const int* __restrict__ cap_slot,
                                                         const double* __restrict__ cap_w, const int* __restrict__ pcp,
-                                                        const double* __restrict__ U, const double* __restrict__ sgr,
+                                                        const double* __restrict__ U, const double* __restrict__ isgr,
                                                         int LUR, double kappa, int nterms,
                                                         const double* __restrict__ base, double c0,
                                                         const double* __restrict__ nearX, double c1,
@@ -747,9 +753,18 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
                                                         const double* __restrict__ ge, double cg,
                                                         double* __restrict__ out) {
   constexpr int L = (LM + 1) * (LM + 1);
-  __shared__ double vA[kMaxN], vB[kMaxN], gR[kMaxN], gE[kMaxN];
-  __shared__ double capA[kCapChunk], capB[kCapChunk];
-  __shared__ double sX[kNbrLds * 2 * L];
+  constexpr int NT = (LM + 1) * (LM + 2) / 2;
+  extern __shared__ double sh[];
+  double* vA = sh;
+  double* vB = vA + N;
+  double* gR = vB + N;
+  double* gE = gR + N;
+  double* capA = gE + N;
+  double* capB = capA + kCapChunk;
+  double* sX = capB + kCapChunk;
+  double* spmm = sX + kNbrLds * 2 * L;
+  double* sra = spmm + (LM + 1);
+  double* srb = sra + NT;
   const int i = blockIdx.x;
   const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2], ri = rad[i];
   const int q0 = nptr[i], K = nptr[i + 1] - q0;
@@ -761,6 +776,11 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
     gR[n] = gr1 ? u * (gr1[(long)i * N + n] + (gr2 ? gr2[(long)i * N + n] : 0.0)) : 0.0;
     gE[n] = ge ? u * ge[(long)i * N + n] : 0.0;
   }
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+    sra[t] = c_ra[t];
+    srb[t] = c_rb[t];
+    if (t <= LM) spmm[t] = c_pmm[t];
+  }
   if (nearX && lds_x) {
     for (int t = threadIdx.x; t < K * 2 * L; t += blockDim.x) {
       const int a = t / (2 * L), r = t - a * 2 * L;
@@ -770,10 +790,11 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
   }
   __syncthreads();
   if (nearX) {
+    const int qd = threadIdx.x & 3, nq = blockDim.x >> 2;
     const int c0i = cptr[i], c1i = cptr[i + 1];
     for (int cb = c0i; cb < c1i; cb += kCapChunk) {
       const int ce = min(c1i, cb + kCapChunk);
-      for (int c = cb + threadIdx.x; c < ce; c += blockDim.x) {
+      for (int c = cb + (threadIdx.x >> 2); c < ce; c += nq) {  // the four lanes of a quad share c
         const int n = cap_n[c], a = cap_slot[c];
         const int j = nidx[q0 + a];
         const double irj = 1.0 / rad[j];
@@ -787,16 +808,22 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
         double sa = 0.0, pb[LM + 1];
 #pragma unroll
         for (int l = 0; l <= LM; ++l) pb[l] = 0.0;
-        for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
+        solid_harmonic_quad<LM>(vx, vy, vz, qd, spmm, sra, srb, [&](int l, int idx, double S) {
           sa += Xr[idx] * S;
           pb[l] += Xe[idx] * S;
         });
         double sb = 0.0;
 #pragma unroll
-        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] / sgr[j * LUR + l];
-        const double w = cap_w[c];
-        capA[c - cb] = w * sa;
-        capB[c - cb] = w * sb;
+        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] * isgr[j * LUR + l];
+        sa += __shfl_xor(sa, 1);
+        sb += __shfl_xor(sb, 1);
+        sa += __shfl_xor(sa, 2);
+        sb += __shfl_xor(sb, 2);
+        if (qd == 0) {
+          const double w = cap_w[c];
+          capA[c - cb] = w * sa;
+          capB[c - cb] = w * sb;
+        }
       }
       __syncthreads();
       for (int n = threadIdx.x; n < N; n += blockDim.x) {
@@ -826,14 +853,23 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
   }
 }
 
-// Transposed near part from reverse cap lists (same result as the near part of k_apply_LTZ).
+// Transposed near part from reverse cap lists (same result as the near part of
+// k_apply_LTZ).  One block of 128 threads per sphere j; caps are taken kLtzChunk at a
+// time: the four lanes of each cap write its harmonics (columns m = q mod 4) and
+// weights to LDS, then one thread per coefficient accumulates over the chunk.
+constexpr int kLtzChunk = 32;
 template <int LM>
-__global__ __launch_bounds__(256) void k_apply_LTZ_caps(int M, int N, int LY, const double* __restrict__ Y,
+__host__ __device__ constexpr size_t k_apply_LTZ_caps_lds_doubles(int N) {
+  return (size_t)(N > kLtzChunk * (LM + 1) * (LM + 1) ? N : kLtzChunk * (LM + 1) * (LM + 1)) + 2 * (LM + 1) * (LM + 1) +
+         kLtzChunk * (LM + 2) + (LM + 1) + (LM + 1) * (LM + 2);
+}
+template <int LM>
+__global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, const double* __restrict__ Y,
                                                          const double* __restrict__ leb, const double* __restrict__ xyz,
                                                          const double* __restrict__ rad, const int* __restrict__ rptr,
                                                          const int* __restrict__ rc_i, const int* __restrict__ rc_n,
                                                          const double* __restrict__ rc_w, const double* __restrict__ U,
-                                                         const double* __restrict__ sgr, const double* __restrict__ ycr,
+                                                         const double* __restrict__ isgr, const double* __restrict__ ycr,
                                                          const double* __restrict__ yce, const double* __restrict__ Cl,
                                                          int LUR, double kappa, int nterms,
                                                          const double* __restrict__ base, double c0,
@@ -841,10 +877,24 @@ __global__ __launch_bounds__(256) void k_apply_LTZ_caps(int M, int N, int LY, co
                                                          double c1, const double* __restrict__ lam, int LLAM,
                                                          double* __restrict__ out) {
   constexpr int L = (LM + 1) * (LM + 1);
-  __shared__ double gg[kMaxN];
-  __shared__ double cl[L], mu[L];
-  __shared__ double red[8 * L];
-  const int j = blockIdx.x;
+  constexpr int NT = (LM + 1) * (LM + 2) / 2;
+  extern __shared__ double sh[];
+  // the harmonics buffer doubles as the point buffer of the single-layer part
+  double* Sb = sh;                                                     // [kLtzChunk][L]
+  double* gg = sh;                                                     // [N]
+  double* cl = sh + (N > kLtzChunk * L ? N : kLtzChunk * L);           // [L]
+  double* mu = cl + L;                                                 // [L]
+  double* fA = mu + L;                                                 // [kLtzChunk]
+  double* fB = fA + kLtzChunk;                                         // [kLtzChunk][LM+1]
+  double* spmm = fB + kLtzChunk * (LM + 1);
+  double* sra = spmm + (LM + 1);
+  double* srb = sra + NT;
+  const int j = blockIdx.x;  // blockDim.x == 128
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+    sra[t] = c_ra[t];
+    srb[t] = c_rb[t];
+    if (t <= LM) spmm[t] = c_pmm[t];
+  }
   if (lam) {
     for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t];
     __syncthreads();
@@ -863,48 +913,60 @@ __global__ __launch_bounds__(256) void k_apply_LTZ_caps(int M, int N, int LY, co
   } else {
     for (int t = threadIdx.x; t < L; t += blockDim.x) mu[t] = 0.0;
   }
-  double accA[L], accB[L];
+  __syncthreads();  // gg is reused as the harmonics buffer
+  constexpr int NA = (L + 127) / 128;  // coefficients per thread: threadIdx.x + 128 r
+  double accA[NA], accB[NA];
 #pragma unroll
-  for (int t = 0; t < L; ++t) { accA[t] = 0.0; accB[t] = 0.0; }
+  for (int r = 0; r < NA; ++r) { accA[r] = 0.0; accB[r] = 0.0; }
   if (zr) {
     const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
-    double isg[LM + 1];
+    const int qd = threadIdx.x & 3, cl4 = threadIdx.x >> 2;  // cap of the quad in the chunk
+    const int r0 = rptr[j], r1 = rptr[j + 1];
+    for (int cb = r0; cb < r1; cb += kLtzChunk) {
+      const int cnt = min(kLtzChunk, r1 - cb);
+      if (cl4 < cnt) {
+        const int c = cb + cl4;
+        const int i = rc_i[c], n = rc_n[c];
+        const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+        const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+        const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+        if (qd == 0) {
+          const double t2 = vx * vx + vy * vy + vz * vz;
+          const double wom = leb[4 * n + 3] * rc_w[c];
+          const double cB = wom * ze[(long)i * N + n];
+          double sg[LM + 1];
+          sigma_weights<LM, double>(kappa * kappa * rj * rj * t2, nterms, sg);
+          fA[cl4] = wom * zr[(long)i * N + n];
 #pragma unroll
-    for (int l = 0; l <= LM; ++l) isg[l] = 1.0 / sgr[j * LUR + l];
-    for (int c = rptr[j] + threadIdx.x; c < rptr[j + 1]; c += blockDim.x) {
-      const int i = rc_i[c], n = rc_n[c];
-      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
-      const double t2 = vx * vx + vy * vy + vz * vz;
-      const double wom = leb[4 * n + 3] * rc_w[c];
-      const double cA = wom * zr[(long)i * N + n], cB = wom * ze[(long)i * N + n];
-      double sg[LM + 1];
-      sigma_weights<LM, double>(kappa * kappa * rj * rj * t2, nterms, sg);
+          for (int l = 0; l <= LM; ++l) fB[cl4 * (LM + 1) + l] = sg[l] * cB * isgr[j * LUR + l];
+        }
+        double* Sr = Sb + cl4 * L;
+        solid_harmonic_quad<LM>(vx, vy, vz, qd, spmm, sra, srb, [&](int, int idx, double S) { Sr[idx] = S; });
+      }
+      __syncthreads();
 #pragma unroll
-      for (int l = 0; l <= LM; ++l) sg[l] *= cB * isg[l];
-      for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) {
-        accA[idx] += cA * S;
-        accB[idx] += sg[l] * S;
-      });
+      for (int r = 0; r < NA; ++r) {
+        const int t = threadIdx.x + 128 * r;
+        if (t < L) {
+          const int tdeg = deg_of(t);
+          for (int c = 0; c < cnt; ++c) {
+            const double S = Sb[c * L + t];
+            accA[r] += fA[c] * S;
+            accB[r] += fB[c * (LM + 1) + tdeg] * S;
+          }
+        }
+      }
+      __syncthreads();
     }
   }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  __syncthreads();
 #pragma unroll
-  for (int t = 0; t < L; ++t) {
-    double a = wave_sum(accA[t]);
-    double b = wave_sum(accB[t]);
-    if (lane == 0) { red[wid * 2 * L + t] = a; red[wid * 2 * L + L + t] = b; }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int w = 0; w < nw; ++w) { a += red[w * 2 * L + t]; b += red[w * 2 * L + L + t]; }
+  for (int r = 0; r < NA; ++r) {
+    const int t = threadIdx.x + 128 * r;
+    if (t >= L) continue;
     const int l = deg_of(t);
     const long ir = (long)j * L + t, ie = (long)(M + j) * L + t;
-    double orr = c1 * a + ycr[j * LUR + l] * mu[t];
-    double oe = c1 * b + yce[j * LUR + l] * mu[t];
+    double orr = c1 * accA[r] + ycr[j * LUR + l] * mu[t];
+    double oe = c1 * accB[r] + yce[j * LUR + l] * mu[t];
     if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
     out[ir] = orr;
     out[ie] = oe;

@@ -1,0 +1,73 @@
+"""ddLPB energy as a torch.autograd.Function (GPU, through the C ABI): the backward
+(adjoint solve + force assembly) against the oracle forces and against central
+finite differences of the energy, and a batch of perturbed conformations against
+independent contexts."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_00552_amd import Context, inputs
+from paper_2203_00552_amd.autograd import DDLPBEnergy
+
+pytestmark = pytest.mark.gpu
+
+
+def test_backward_is_minus_oracle_forces():
+    x, r, q = inputs.small_cluster(0)
+    model = DDLPBEnergy(r, q, tol=1e-11, lmax=6, n_lebedev=110)
+    X = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    E = model(X)
+    E.backward()
+    ref = oracle.Problem(x, r, q, lmax=6, n_lebedev=110).solve("dense")
+    assert abs(E.item() / ref["energy"] - 1) < 1e-8
+    F = ref["forces"]
+    assert np.abs(X.grad.numpy() + F).max() < 1e-8 * np.abs(F).max()
+    model.close()
+
+
+def test_backward_matches_central_differences():
+    """Central differences (h = 1e-4 A) of the FP64 direct-sum energy on 20 seeded
+    atoms x 3 coordinates of a 300-atom cluster."""
+    x, r, q = inputs.lattice_cluster(300, seed=8)
+    model = DDLPBEnergy(r, q, tol=1e-11, lmax=6, n_lebedev=110)
+    X = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    model(X).backward()
+    g = X.grad.numpy()
+    rng = np.random.default_rng(9)
+    atoms = rng.choice(len(r), 20, replace=False)
+    h = 1e-4
+    err = 0.0
+    with torch.no_grad():
+        for a in atoms:
+            for c in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[a, c] += h
+                xm[a, c] -= h
+                fd = (model(torch.tensor(xp)).item() - model(torch.tensor(xm)).item()) / (2 * h)
+                err = max(err, abs(fd - g[a, c]))
+    assert err < 1e-5 * np.abs(g).max(), err
+    model.close()
+
+
+def test_batch_of_perturbed_conformations():
+    """16 conformations of a 2,000-atom cluster (Gaussian displacements 0.05 A), FMM
+    p = 12: energies and gradients equal those of independent contexts."""
+    x, r, q = inputs.lattice_cluster(2000, seed=10)
+    rng = np.random.default_rng(12)
+    B = 16
+    xs = x[None] + 0.05 * rng.normal(size=(B,) + x.shape)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    model = DDLPBEnergy(r, q, tol=1e-8, **kw)
+    X = torch.tensor(xs, requires_grad=True)
+    E = model(X)
+    E.sum().backward()
+    for b in (0, 7, 15):
+        c = Context(xs[b], r, q, **kw)
+        Eb = c.solve(1e-8)
+        c.adjoint(1e-8)
+        Fb = c.forces()
+        assert abs(E[b].item() / Eb - 1) < 1e-12
+        assert np.abs(X.grad[b].numpy() + Fb).max() < 1e-10 * np.abs(Fb).max()
+        c.close()
+    model.close()

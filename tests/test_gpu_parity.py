@@ -93,3 +93,18 @@ def test_edge_cases_gpu():
     ref = P.solve("dense")
     assert abs(E / ref["energy"] - 1) < 1e-8
     assert _relF(F, ref["forces"]) < 1e-8
+
+
+def test_apply_dense_overlaps_lmax8():
+    """Operator applications where spheres have more than 16 neighbours and more than
+    512 caps (the global-memory neighbour path and several cap chunks)."""
+    x, r, q = inputs.lattice_cluster(48, seed=2, spacing=1.5)
+    ctx, P = _pair(x, r, q, 8, 302)
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(2, P.M, P.L))
+    for tr in (False, True):
+        Y = ctx.apply(X, transpose=tr)
+        Yo = P.apply(X, transpose=tr)
+        assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max(), tr
+    _, _, nn = P.grid_fields()
+    assert nn.max() > 16 and ctx.stats()["n_cap_pairs"] > 512 * len(r) // 4
