@@ -119,8 +119,13 @@ void ddlpb_free(ddlpb_ctx* ctx);
  * ddlpb_set_option -- set a tuning option before the first solve (else ESTATE
  * for options that change the discrete problem: eta, precision, fmm_order).
  *   "eta"            switching width of chi_eta (Sec. 3.1), 0 < eta <= 1
- *   "precision"      0 = FP64 everywhere, 1 = mixed (FP32 matvec kernels, FP64
- *                    Krylov/reductions/Bessel ratios, FP64 outer refinement)
+ *   "precision"      0 = FP64 everywhere; 1 = mixed: FP64 iterative refinement
+ *                    (FP64 residual b - L x) around GMRES solves of the correction
+ *                    equation in which the near-field A/B kernels (operator and
+ *                    Jacobi sweeps) compute in FP32; Krylov vectors,
+ *                    orthogonalisation, norms, Bessel ratios, the FMM and the
+ *                    single-layer sums stay FP64 (stats.refinements counts the
+ *                    refinement steps).  Needs the cap lists (else FP64 is used).
  *   "gmres_restart"  outer Krylov subspace size (1..200)
  *   "inner_sweeps"   Jacobi sweeps on L_AB = [A 0; 0 B] used as the innermost
  *                    preconditioner (0..64; Sec. 4 uses L_AB as preconditioner)
@@ -135,6 +140,10 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
  *   "warm_start"     1 (default): solves start from the previous X / X_adj;
  *                    0: every solve starts from zero
+ *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field kernels of the mixed
+ *                    path (diagnostic: operator error of the mixed path)
+ *   "m2l_waves"      wavefronts per block of the multipole-to-local kernel
+ *                    (0 = chosen from the occupancy calculator; 1, 2, 4, 8, 16)
  *   "kernel_timing"  1: record the device time of every kernel launch with HIP
  *                    events on the context's stream (see ddlpb_kernel_times)
  * Errors: EINVAL (unknown key or value out of range), ESTATE.

@@ -68,6 +68,9 @@ struct ddlpb_ctx {
   const ddlpb_tables::LebedevRule* rule = nullptr;
   // ---- options
   int precision = 0, restart = 100, sweeps = 24, maxit = 400, leaf = 32;
+  int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
+  double *d_rr = nullptr, *d_dd = nullptr;
+  bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
@@ -334,6 +337,8 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_Vin = two_level ? cv.take<double>((size_t)(c->inner_iters + 1) * D) : nullptr;
   c->d_t4 = cv.take<double>(D);
   c->d_t5 = cv.take<double>(D);
+  c->d_rr = c->precision == 1 ? cv.take<double>(D) : nullptr;  // residual and correction of the mixed path
+  c->d_dd = c->precision == 1 ? cv.take<double>(D) : nullptr;
   c->d_pptr = cv.take<int>(M + 1);
   c->cap_cap = std::max(c->cap_cap, c->cap_est);
   c->d_cptr = cv.take<int>(M + 1);
@@ -536,21 +541,43 @@ void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, dou
   HIPCHK(hipGetLastError());
 }
 
+// near-field A/B kernels over the cap lists in compute type R (float on the mixed path)
+template <class R>
+void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
+                    const double* gr2, const double* ge, double cg, double* out) {
+  LM_DISPATCH(c->lmax, {
+    const size_t lds = k_apply_LX_caps_lds_entries<LMc>(c->N) * sizeof(R);
+    if (lds > 65536)
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LX_caps<LMc, R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_apply_LX_caps<LMc, R>), dim3(c->M), dim3(256), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
+                       c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_cptr, c->d_capn, c->d_capslot,
+                       c->d_capw, c->d_pcp, c->d_U, c->d_isgr, c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1,
+                       gr2, ge, cg, out);
+  });
+  HIPCHK(hipGetLastError());
+}
+template <class R>
+void launch_LTZ_caps(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
+                     const double* lam, int llam, double* out) {
+  LM_DISPATCH(c->lmax, {
+    const size_t lds = k_apply_LTZ_caps_lds_entries<LMc>(c->N) * sizeof(R);
+    if (lds > 65536)
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LTZ_caps<LMc, R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_apply_LTZ_caps<LMc, R>), dim3(c->M), dim3(128), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
+                       c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw, c->d_U, c->d_isgr,
+                       c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam, out);
+  });
+  HIPCHK(hipGetLastError());
+}
+
 void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
               const double* gr2, const double* ge, double cg, double* out) {
   KScope ks(c, "apply_LX", nearX ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
-    LM_DISPATCH(c->lmax, {
-      const size_t lds = k_apply_LX_caps_lds_doubles<LMc>(c->N) * sizeof(double);
-      if (lds > 65536)
-        HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LX_caps<LMc>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL((k_apply_LX_caps<LMc>), dim3(c->M), dim3(256), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
-                         c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_cptr, c->d_capn, c->d_capslot,
-                         c->d_capw, c->d_pcp, c->d_U, c->d_isgr, c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1,
-                         gr2, ge, cg, out);
-    });
-    HIPCHK(hipGetLastError());
+    if (c->cur_prec == 1) launch_LX_caps<float>(c, base, c0, nearX, c1, gr1, gr2, ge, cg, out);
+    else launch_LX_caps<double>(c, base, c0, nearX, c1, gr1, gr2, ge, cg, out);
     return;
   }
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LX<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
@@ -570,17 +597,8 @@ void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, co
                const double* lam, int llam, double* out) {
   KScope ks(c, "apply_LTZ", zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
-    LM_DISPATCH(c->lmax, {
-      const size_t lds = k_apply_LTZ_caps_lds_doubles<LMc>(c->N) * sizeof(double);
-      if (lds > 65536)
-        HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LTZ_caps<LMc>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL((k_apply_LTZ_caps<LMc>), dim3(c->M), dim3(128), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
-                         c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw, c->d_U, c->d_isgr,
-                         c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam,
-                         out);
-    });
-    HIPCHK(hipGetLastError());
+    if (c->cur_prec == 1) launch_LTZ_caps<float>(c, base, c0, zr, ze, c1, lam, llam, out);
+    else launch_LTZ_caps<double>(c, base, c0, zr, ze, c1, lam, llam, out);
     return;
   }
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_apply_LTZ<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
@@ -610,7 +628,7 @@ void sl_field_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double*
 void sl_adjoint_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double* cgrid, int lo, int exclude_self,
                      int accumulate, int ldl, double* lam) {
   KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pairs_pts);
-  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(128), 0, c->stream, c->M, c->N,
                                      c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_ur,
                                      c->LUR, c->kappa, exclude_self, accumulate, ldl, lam));
   HIPCHK(hipGetLastError());
@@ -836,7 +854,7 @@ void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self
   if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
   {
     KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pts_fmm);
-    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
+    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(128), 0, c->stream, c->M, c->N,
                                        c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, cgrid,
                                        c->d_ur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
     HIPCHK(hipGetLastError());
@@ -1020,6 +1038,59 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
                     c->d_t1, c->d_t2, iters, relres);
 }
 
+// L x = b (or L^T x = b).  FP64: GMRES.  Mixed: FP64 iterative refinement around
+// GMRES solves of the correction equation with the FP32 near-field kernels (FP64
+// Krylov vectors, orthogonalisation and norms); each correction is solved to the
+// relative tolerance that would meet tol, but not below kInnerFloor, and the FP64
+// residual decides when to stop.
+// The FP32 operator is linear only up to single-precision rounding, so an inner
+// solve cannot go much below cond(L) * 1e-7; corrections are solved to at most
+// 1e-4 relative and at most one Krylov cycle each, and the refinement contracts.
+constexpr int kMaxRefine = 10;
+constexpr double kInnerFloor = 1e-4;
+int solve_system(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
+  c->cur_prec = 0;
+  if (c->precision == 0 || !c->use_caps || !c->d_rr) {
+    c->stats.refinements = 0;
+    return gmres(c, transpose, b, x, tol, iters, relres);
+  }
+  const long D = 2L * c->M * c->L;
+  const double bn = norm2(c, b);
+  if (bn == 0.0) {
+    fill(c, x, D, 0.0);
+    *iters = 0;
+    *relres = 0.0;
+    c->stats.refinements = 0;
+    return DDLPB_OK;
+  }
+  const int maxit = c->maxit;
+  int total = 0, refs = 0;
+  double rel = 0.0;
+  for (;;) {
+    if (transpose) op_LT(c, x, c->d_rr);
+    else op_L(c, x, c->d_rr);
+    axpby(c, 1.0, b, -1.0, c->d_rr);  // r = b - L x (FP64 operator)
+    rel = norm2(c, c->d_rr) / bn;
+    if (rel <= tol || refs >= kMaxRefine || total >= maxit) break;
+    const double tin = std::min(0.5, std::max(0.5 * tol / rel, kInnerFloor));
+    fill(c, c->d_dd, D, 0.0);
+    int it = 0;
+    double rr = 0.0;
+    c->cur_prec = 1;
+    c->maxit = std::min(maxit - total, c->restart);
+    (void)gmres(c, transpose, c->d_rr, c->d_dd, tin, &it, &rr);
+    c->maxit = maxit;
+    c->cur_prec = 0;
+    axpby(c, 1.0, c->d_dd, 1.0, x);  // x += d
+    total += it;
+    ++refs;
+  }
+  c->stats.refinements = refs;
+  *iters = total;
+  *relres = rel;
+  return rel <= tol ? DDLPB_OK : DDLPB_ENOCONV;
+}
+
 // ------------------------------------------------------------ device setup
 void upload_and_init(ddlpb_ctx* c) {
   ensure_constants();
@@ -1169,7 +1240,7 @@ void geometry_on_device(ddlpb_ctx* c) {
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     size_t need = 0;
-    LM_DISPATCH(c->lmax, need = std::max(k_apply_LX_caps_lds_doubles<LMc>(N), k_apply_LTZ_caps_lds_doubles<LMc>(N)) *
+    LM_DISPATCH(c->lmax, need = std::max(k_apply_LX_caps_lds_entries<LMc>(N), k_apply_LTZ_caps_lds_entries<LMc>(N)) *
                                 sizeof(double));
     c->use_caps = (size_t)c->ncap <= c->cap_cap && need <= (size_t)maxlds;
   }
@@ -1319,7 +1390,7 @@ int ddlpb_solve(ddlpb_ctx* c, double tol, double* energy_out) {
     int it = 0;
     double rel = 0;
     if (!c->warm_start) fill(c, c->d_X, 2L * c->M * c->L, 0.0);
-    rc = gmres(c, false, c->d_g, c->d_X, tol, &it, &rel);
+    rc = solve_system(c, false, c->d_g, c->d_X, tol, &it, &rel);
     c->stats.iters_primal = it;
     c->stats.resid_primal = rel;
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c->stream, c->M, c->L, c->d_X, c->d_q, c->d_scal);
@@ -1344,7 +1415,7 @@ int ddlpb_adjoint(ddlpb_ctx* c, double tol) {
     int it = 0;
     double rel = 0;
     if (!c->warm_start) fill(c, c->d_Xa, 2L * c->M * c->L, 0.0);
-    int rc = gmres(c, true, c->d_Q, c->d_Xa, tol, &it, &rel);
+    int rc = solve_system(c, true, c->d_Q, c->d_Xa, tol, &it, &rel);
     HIPCHK(hipStreamSynchronize(c->stream));
     c->stats.iters_adjoint = it;
     c->stats.resid_adjoint = rel;
@@ -1503,6 +1574,8 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 1 && v <= 4096)) return DDLPB_EINVAL;
     c->leaf = (int)v;
+  } else if (k == "apply_fp32") {
+    c->apply_fp32 = v != 0;
   } else if (k == "m2l_waves") {
     if (!(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
@@ -1679,7 +1752,9 @@ int ddlpb_apply(ddlpb_ctx* c, int32_t transpose, const double* x_in, double* y_o
     if (rc) return rc;
     const size_t D = 2L * c->M * c->L;
     HIPCHK(hipMemcpyAsync(c->d_t2, x_in, D * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    c->cur_prec = c->apply_fp32 ? 1 : 0;
     if (transpose) op_LT(c, c->d_t2, c->d_w); else op_L(c, c->d_t2, c->d_w);
+    c->cur_prec = 0;
     HIPCHK(hipMemcpyAsync(y_out, c->d_w, D * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DDLPB_OK;

@@ -104,26 +104,26 @@ __device__ __forceinline__ void for_each_solid_harmonic(const T& x, const T& y, 
 // The same harmonics split over four lanes: the lane with q = 0..3 produces the
 // columns m = q, q+4, q+8, ... (both signs), in increasing l; pmm/ra/rb are the
 // recurrence constants (copies of c_pmm/c_ra/c_rb, e.g. in LDS).
-template <int LM, class F>
-__device__ __forceinline__ void solid_harmonic_quad(double x, double y, double z, int q, const double* pmm,
-                                                    const double* ra, const double* rb, F&& f) {
+template <int LM, class R, class F>
+__device__ __forceinline__ void solid_harmonic_quad(R x, R y, R z, int q, const R* pmm, const R* ra, const R* rb,
+                                                    F&& f) {
   constexpr int NC = LM / 4 + 1;
-  const double r2 = x * x + y * y + z * z;
-  double cq = 1.0, sq = 0.0;  // (x + i y)^q
+  const R r2 = x * x + y * y + z * z;
+  R cq = R(1), sq = R(0);  // (x + i y)^q
   for (int k = 0; k < q; ++k) {
-    const double c2 = x * cq - y * sq;
+    const R c2 = x * cq - y * sq;
     sq = x * sq + y * cq;
     cq = c2;
   }
-  const double c2 = x * x - y * y, s2 = 2.0 * x * y;
-  const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * c2 * s2;
-  double cm[NC], sm[NC], p1[NC], p2[NC];
+  const R c2 = x * x - y * y, s2 = R(2) * x * y;
+  const R c4 = c2 * c2 - s2 * s2, s4 = R(2) * c2 * s2;
+  R cm[NC], sm[NC], p1[NC], p2[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     if (k == 0) { cm[0] = cq; sm[0] = sq; }
     else { cm[k] = cm[k - 1] * c4 - sm[k - 1] * s4; sm[k] = cm[k - 1] * s4 + sm[k - 1] * c4; }
-    p1[k] = 0.0;
-    p2[k] = 0.0;
+    p1[k] = R(0);
+    p2[k] = R(0);
   }
 #pragma unroll
   for (int l = 0; l <= LM; ++l) {
@@ -131,7 +131,7 @@ __device__ __forceinline__ void solid_harmonic_quad(double x, double y, double z
     for (int k = 0; k < NC; ++k) {
       const int m = q + 4 * k;
       if (m > l) continue;
-      double p;
+      R p;
       if (m == l) p = pmm[m];
       else if (m == l - 1) p = ra[tri(l, m)] * (z * p1[k]);
       else p = ra[tri(l, m)] * (z * p1[k]) - rb[tri(l, m)] * (r2 * p2[k]);

@@ -301,8 +301,13 @@ __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, c
 
 // Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
 // for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
+// One block of 128 threads per sphere j; the active points of each listed sphere are
+// taken kSlaChunk at a time: the four lanes of a point write its harmonics (columns
+// m = q mod 4) and degree weights to LDS, then one thread per coefficient
+// accumulates over the chunk (in point order: deterministic).
+constexpr int kSlaChunk = 32;
 template <int LMO>
-__global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
+__global__ __launch_bounds__(128) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
                                                           const int* __restrict__ act_n, const double* __restrict__ xyz,
                                                           const double* __restrict__ rad, const double* __restrict__ leb,
                                                           const int* __restrict__ lptr, const int* __restrict__ lidx,
@@ -310,44 +315,64 @@ __global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int
                                                           int LUR, double kappa, int exclude_self, int accumulate,
                                                           int LDL, double* __restrict__ lam) {
   constexpr int LO = (LMO + 1) * (LMO + 1);
-  __shared__ double red[4 * LO];
-  const int j = blockIdx.x;
+  constexpr int NT = (LMO + 1) * (LMO + 2) / 2;
+  constexpr int NA = (LO + 127) / 128;
+  __shared__ double Sb[kSlaChunk * LO];
+  __shared__ double fw[kSlaChunk * (LMO + 1)];
+  __shared__ double spmm[LMO + 1], sra[NT], srb[NT], siu[LMO + 1];
+  const int j = blockIdx.x;  // blockDim.x == 128
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+    sra[t] = c_ra[t];
+    srb[t] = c_rb[t];
+    if (t <= LMO) {
+      spmm[t] = c_pmm[t];
+      siu[t] = 1.0 / ur[j * LUR + t];
+    }
+  }
   const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
-  double iu[LMO + 1];
+  const int qd = threadIdx.x & 3, cl4 = threadIdx.x >> 2;
+  double acc[NA];
 #pragma unroll
-  for (int l = 0; l <= LMO; ++l) iu[l] = 1.0 / ur[j * LUR + l];
-  double acc[LO];
-#pragma unroll
-  for (int t = 0; t < LO; ++t) acc[t] = 0.0;
+  for (int r = 0; r < NA; ++r) acc[r] = 0.0;
+  __syncthreads();
   for (int q = lptr[j]; q < lptr[j + 1]; ++q) {
     const int i = lidx[q];
     if (exclude_self && i == j) continue;
-    for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x) {
-      const int n = act_n[k];
-      const double c = cgrid[(long)i * N + n];
-      if (c == 0.0) continue;
-      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
-      const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
-      double u[LMO + 1];
-      k_weights<LMO, double>(rho, kappa, u);
+    const int k0 = act_ptr[i], k1 = act_ptr[i + 1];
+    for (int kb = k0; kb < k1; kb += kSlaChunk) {
+      const int cnt = min(kSlaChunk, k1 - kb);
+      if (cl4 < cnt) {
+        const int n = act_n[kb + cl4];
+        const double c = cgrid[(long)i * N + n];
+        const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+        const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+        const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+        if (qd == 0) {
+          const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
+          double u[LMO + 1];
+          k_weights<LMO, double>(rho, kappa, u);
 #pragma unroll
-      for (int l = 0; l <= LMO; ++l) u[l] *= c * iu[l];
-      for_each_solid_harmonic<LMO, double>(vx, vy, vz, [&](int l, int idx, double S) { acc[idx] += u[l] * S; });
+          for (int l = 0; l <= LMO; ++l) fw[cl4 * (LMO + 1) + l] = u[l] * c * siu[l];
+        }
+        double* Sr = Sb + cl4 * LO;
+        solid_harmonic_quad<LMO, double>(vx, vy, vz, qd, spmm, sra, srb, [&](int, int idx, double S) { Sr[idx] = S; });
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NA; ++r) {
+        const int t = threadIdx.x + 128 * r;
+        if (t < LO) {
+          const int l = deg_of(t);
+          for (int c = 0; c < cnt; ++c) acc[r] += fw[c * (LMO + 1) + l] * Sb[c * LO + t];
+        }
+      }
+      __syncthreads();
     }
   }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < LO; ++t) {
-    double v = wave_sum(acc[t]);
-    if (lane == 0) red[wid * LO + t] = v;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < LO; t += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * LO + t];
-    lam[(long)j * LDL + t] = (accumulate ? lam[(long)j * LDL + t] : 0.0) + s;
+  for (int r = 0; r < NA; ++r) {
+    const int t = threadIdx.x + 128 * r;
+    if (t < LO) lam[(long)j * LDL + t] = (accumulate ? lam[(long)j * LDL + t] : 0.0) + acc[r];
   }
 }
 
@@ -734,11 +759,13 @@ __global__ void k_rcaps_fill(int M, int N, const double* __restrict__ xyz, const
 // (deterministic), then the An transforms.  Dynamic LDS: k_apply_LX_caps_lds().
 constexpr int kCapChunk = 512;
 constexpr int kNbrLds = 16;
+// LDS entries (of the compute type) of k_apply_LX_caps
 template <int LM>
-__host__ __device__ constexpr size_t k_apply_LX_caps_lds_doubles(int N) {
+__host__ __device__ constexpr size_t k_apply_LX_caps_lds_entries(int N) {
   return 4 * (size_t)N + 2 * kCapChunk + (size_t)kNbrLds * 2 * (LM + 1) * (LM + 1) + (LM + 1) + (LM + 1) * (LM + 2);
 }
-template <int LM>
+// R: compute type (double, or float on the mixed path); inputs and outputs are FP64
+template <int LM, class R>
 __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, const double* __restrict__ Y,
                                                         const double* __restrict__ leb, const double* __restrict__ xyz,
                                                         const double* __restrict__ rad, const int* __restrict__ nptr,
@@ -754,38 +781,38 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
                                                         double* __restrict__ out) {
   constexpr int L = (LM + 1) * (LM + 1);
   constexpr int NT = (LM + 1) * (LM + 2) / 2;
-  extern __shared__ double sh[];
-  double* vA = sh;
-  double* vB = vA + N;
-  double* gR = vB + N;
-  double* gE = gR + N;
-  double* capA = gE + N;
-  double* capB = capA + kCapChunk;
-  double* sX = capB + kCapChunk;
-  double* spmm = sX + kNbrLds * 2 * L;
-  double* sra = spmm + (LM + 1);
-  double* srb = sra + NT;
+  extern __shared__ double sh_raw[];
+  R* vA = reinterpret_cast<R*>(sh_raw);
+  R* vB = vA + N;
+  R* gR = vB + N;
+  R* gE = gR + N;
+  R* capA = gE + N;
+  R* capB = capA + kCapChunk;
+  R* sX = capB + kCapChunk;
+  R* spmm = sX + kNbrLds * 2 * L;
+  R* sra = spmm + (LM + 1);
+  R* srb = sra + NT;
   const int i = blockIdx.x;
   const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2], ri = rad[i];
   const int q0 = nptr[i], K = nptr[i + 1] - q0;
   const bool lds_x = K <= kNbrLds;
   for (int n = threadIdx.x; n < N; n += blockDim.x) {
-    vA[n] = 0.0;
-    vB[n] = 0.0;
+    vA[n] = R(0);
+    vB[n] = R(0);
     const double u = U[(long)i * N + n];
-    gR[n] = gr1 ? u * (gr1[(long)i * N + n] + (gr2 ? gr2[(long)i * N + n] : 0.0)) : 0.0;
-    gE[n] = ge ? u * ge[(long)i * N + n] : 0.0;
+    gR[n] = R(gr1 ? u * (gr1[(long)i * N + n] + (gr2 ? gr2[(long)i * N + n] : 0.0)) : 0.0);
+    gE[n] = R(ge ? u * ge[(long)i * N + n] : 0.0);
   }
   for (int t = threadIdx.x; t < NT; t += blockDim.x) {
-    sra[t] = c_ra[t];
-    srb[t] = c_rb[t];
-    if (t <= LM) spmm[t] = c_pmm[t];
+    sra[t] = R(c_ra[t]);
+    srb[t] = R(c_rb[t]);
+    if (t <= LM) spmm[t] = R(c_pmm[t]);
   }
   if (nearX && lds_x) {
     for (int t = threadIdx.x; t < K * 2 * L; t += blockDim.x) {
       const int a = t / (2 * L), r = t - a * 2 * L;
       const int j = nidx[q0 + a];
-      sX[t] = r < L ? nearX[(long)j * L + r] : nearX[(long)(M + j) * L + r - L];
+      sX[t] = R(r < L ? nearX[(long)j * L + r] : nearX[(long)(M + j) * L + r - L]);
     }
   }
   __syncthreads();
@@ -798,29 +825,37 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
         const int n = cap_n[c], a = cap_slot[c];
         const int j = nidx[q0 + a];
         const double irj = 1.0 / rad[j];
-        const double vx = (xi + ri * leb[4 * n] - xyz[3 * j]) * irj, vy = (yi + ri * leb[4 * n + 1] - xyz[3 * j + 1]) * irj,
-                     vz = (zi + ri * leb[4 * n + 2] - xyz[3 * j + 2]) * irj;
-        const double t2 = vx * vx + vy * vy + vz * vz;
-        double sg[LM + 1];
-        sigma_weights<LM, double>(kappa * kappa * rad[j] * rad[j] * t2, nterms, sg);
-        const double* Xr = lds_x ? sX + a * 2 * L : nearX + (long)j * L;
-        const double* Xe = lds_x ? sX + a * 2 * L + L : nearX + (long)(M + j) * L;
-        double sa = 0.0, pb[LM + 1];
+        const R vx = R((xi + ri * leb[4 * n] - xyz[3 * j]) * irj), vy = R((yi + ri * leb[4 * n + 1] - xyz[3 * j + 1]) * irj),
+                vz = R((zi + ri * leb[4 * n + 2] - xyz[3 * j + 2]) * irj);
+        const R t2 = vx * vx + vy * vy + vz * vz;
+        R sg[LM + 1];
+        sigma_weights<LM, R>(R(kappa * kappa * rad[j] * rad[j]) * t2, nterms, sg);
+        R sa = R(0), sb = R(0), pb[LM + 1];
 #pragma unroll
-        for (int l = 0; l <= LM; ++l) pb[l] = 0.0;
-        solid_harmonic_quad<LM>(vx, vy, vz, qd, spmm, sra, srb, [&](int l, int idx, double S) {
-          sa += Xr[idx] * S;
-          pb[l] += Xe[idx] * S;
-        });
-        double sb = 0.0;
+        for (int l = 0; l <= LM; ++l) pb[l] = R(0);
+        if (lds_x) {
+          const R* Xr = sX + a * 2 * L;
+          const R* Xe = Xr + L;
+          solid_harmonic_quad<LM, R>(vx, vy, vz, qd, spmm, sra, srb, [&](int l, int idx, R S) {
+            sa += Xr[idx] * S;
+            pb[l] += Xe[idx] * S;
+          });
+        } else {
+          const double* Xr = nearX + (long)j * L;
+          const double* Xe = nearX + (long)(M + j) * L;
+          solid_harmonic_quad<LM, R>(vx, vy, vz, qd, spmm, sra, srb, [&](int l, int idx, R S) {
+            sa += R(Xr[idx]) * S;
+            pb[l] += R(Xe[idx]) * S;
+          });
+        }
 #pragma unroll
-        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] * isgr[j * LUR + l];
+        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] * R(isgr[j * LUR + l]);
         sa += __shfl_xor(sa, 1);
         sb += __shfl_xor(sb, 1);
         sa += __shfl_xor(sa, 2);
         sb += __shfl_xor(sb, 2);
         if (qd == 0) {
-          const double w = cap_w[c];
+          const R w = R(cap_w[c]);
           capA[c - cb] = w * sa;
           capB[c - cb] = w * sb;
         }
@@ -828,7 +863,7 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
       __syncthreads();
       for (int n = threadIdx.x; n < N; n += blockDim.x) {
         const int p0 = max(pcp[(long)i * (N + 1) + n], cb), p1 = min(pcp[(long)i * (N + 1) + n + 1], ce);
-        double a = 0.0, b = 0.0;
+        R a = R(0), b = R(0);
         for (int c = p0; c < p1; ++c) { a += capA[c - cb]; b += capB[c - cb]; }
         vA[n] += a;
         vB[n] += b;
@@ -837,16 +872,16 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
     }
   }
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double sa = 0.0, sb = 0.0, sr = 0.0, se = 0.0;
+    R sa = R(0), sb = R(0), sr = R(0), se = R(0);
     for (int n = 0; n < N; ++n) {
-      const double wy = leb[4 * n + 3] * Y[(long)n * LY + t];
+      const R wy = R(leb[4 * n + 3] * Y[(long)n * LY + t]);
       sa += wy * vA[n];
       sb += wy * vB[n];
       sr += wy * gR[n];
       se += wy * gE[n];
     }
     const long ir = (long)i * L + t, ie = (long)(M + i) * L + t;
-    double orr = c1 * sa + cg * sr, oe = c1 * sb + cg * se;
+    double orr = c1 * (double)sa + cg * (double)sr, oe = c1 * (double)sb + cg * (double)se;
     if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
     out[ir] = orr;
     out[ie] = oe;
@@ -859,11 +894,11 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
 // weights to LDS, then one thread per coefficient accumulates over the chunk.
 constexpr int kLtzChunk = 32;
 template <int LM>
-__host__ __device__ constexpr size_t k_apply_LTZ_caps_lds_doubles(int N) {
+__host__ __device__ constexpr size_t k_apply_LTZ_caps_lds_entries(int N) {
   return (size_t)(N > kLtzChunk * (LM + 1) * (LM + 1) ? N : kLtzChunk * (LM + 1) * (LM + 1)) + 2 * (LM + 1) * (LM + 1) +
          kLtzChunk * (LM + 2) + (LM + 1) + (LM + 1) * (LM + 2);
 }
-template <int LM>
+template <int LM, class R>
 __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, const double* __restrict__ Y,
                                                          const double* __restrict__ leb, const double* __restrict__ xyz,
                                                          const double* __restrict__ rad, const int* __restrict__ rptr,
@@ -878,46 +913,47 @@ __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, co
                                                          double* __restrict__ out) {
   constexpr int L = (LM + 1) * (LM + 1);
   constexpr int NT = (LM + 1) * (LM + 2) / 2;
-  extern __shared__ double sh[];
+  extern __shared__ double sh_raw[];
+  R* sh = reinterpret_cast<R*>(sh_raw);
   // the harmonics buffer doubles as the point buffer of the single-layer part
-  double* Sb = sh;                                                     // [kLtzChunk][L]
-  double* gg = sh;                                                     // [N]
-  double* cl = sh + (N > kLtzChunk * L ? N : kLtzChunk * L);           // [L]
-  double* mu = cl + L;                                                 // [L]
-  double* fA = mu + L;                                                 // [kLtzChunk]
-  double* fB = fA + kLtzChunk;                                         // [kLtzChunk][LM+1]
-  double* spmm = fB + kLtzChunk * (LM + 1);
-  double* sra = spmm + (LM + 1);
-  double* srb = sra + NT;
+  R* Sb = sh;                                                      // [kLtzChunk][L]
+  R* gg = sh;                                                      // [N]
+  R* cl = sh + (N > kLtzChunk * L ? N : kLtzChunk * L);            // [L]
+  R* mu = cl + L;                                                  // [L]
+  R* fA = mu + L;                                                  // [kLtzChunk]
+  R* fB = fA + kLtzChunk;                                          // [kLtzChunk][LM+1]
+  R* spmm = fB + kLtzChunk * (LM + 1);
+  R* sra = spmm + (LM + 1);
+  R* srb = sra + NT;
   const int j = blockIdx.x;  // blockDim.x == 128
   for (int t = threadIdx.x; t < NT; t += blockDim.x) {
-    sra[t] = c_ra[t];
-    srb[t] = c_rb[t];
-    if (t <= LM) spmm[t] = c_pmm[t];
+    sra[t] = R(c_ra[t]);
+    srb[t] = R(c_rb[t]);
+    if (t <= LM) spmm[t] = R(c_pmm[t]);
   }
   if (lam) {
-    for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t];
+    for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = R(Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t]);
     __syncthreads();
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
       const double* Yn = Y + (long)n * LY;
-      double a = 0.0;
-      for (int t = 0; t < L; ++t) a += Yn[t] * cl[t];
-      gg[n] = U[(long)j * N + n] * a;
+      R a = R(0);
+      for (int t = 0; t < L; ++t) a += R(Yn[t]) * cl[t];
+      gg[n] = R(U[(long)j * N + n]) * a;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
-      double a = 0.0;
-      for (int n = 0; n < N; ++n) a += leb[4 * n + 3] * Y[(long)n * LY + t] * gg[n];
+      R a = R(0);
+      for (int n = 0; n < N; ++n) a += R(leb[4 * n + 3] * Y[(long)n * LY + t]) * gg[n];
       mu[t] = a;
     }
   } else {
-    for (int t = threadIdx.x; t < L; t += blockDim.x) mu[t] = 0.0;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) mu[t] = R(0);
   }
   __syncthreads();  // gg is reused as the harmonics buffer
   constexpr int NA = (L + 127) / 128;  // coefficients per thread: threadIdx.x + 128 r
-  double accA[NA], accB[NA];
+  R accA[NA], accB[NA];
 #pragma unroll
-  for (int r = 0; r < NA; ++r) { accA[r] = 0.0; accB[r] = 0.0; }
+  for (int r = 0; r < NA; ++r) { accA[r] = R(0); accB[r] = R(0); }
   if (zr) {
     const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
     const int qd = threadIdx.x & 3, cl4 = threadIdx.x >> 2;  // cap of the quad in the chunk
@@ -927,21 +963,21 @@ __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, co
       if (cl4 < cnt) {
         const int c = cb + cl4;
         const int i = rc_i[c], n = rc_n[c];
-        const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-        const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-        const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+        const R vx = R((xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj);
+        const R vy = R((xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj);
+        const R vz = R((xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj);
         if (qd == 0) {
-          const double t2 = vx * vx + vy * vy + vz * vz;
+          const R t2 = vx * vx + vy * vy + vz * vz;
           const double wom = leb[4 * n + 3] * rc_w[c];
-          const double cB = wom * ze[(long)i * N + n];
-          double sg[LM + 1];
-          sigma_weights<LM, double>(kappa * kappa * rj * rj * t2, nterms, sg);
-          fA[cl4] = wom * zr[(long)i * N + n];
+          const R cB = R(wom * ze[(long)i * N + n]);
+          R sg[LM + 1];
+          sigma_weights<LM, R>(R(kappa * kappa * rj * rj) * t2, nterms, sg);
+          fA[cl4] = R(wom * zr[(long)i * N + n]);
 #pragma unroll
-          for (int l = 0; l <= LM; ++l) fB[cl4 * (LM + 1) + l] = sg[l] * cB * isgr[j * LUR + l];
+          for (int l = 0; l <= LM; ++l) fB[cl4 * (LM + 1) + l] = sg[l] * cB * R(isgr[j * LUR + l]);
         }
-        double* Sr = Sb + cl4 * L;
-        solid_harmonic_quad<LM>(vx, vy, vz, qd, spmm, sra, srb, [&](int, int idx, double S) { Sr[idx] = S; });
+        R* Sr = Sb + cl4 * L;
+        solid_harmonic_quad<LM, R>(vx, vy, vz, qd, spmm, sra, srb, [&](int, int idx, R S) { Sr[idx] = S; });
       }
       __syncthreads();
 #pragma unroll
@@ -950,7 +986,7 @@ __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, co
         if (t < L) {
           const int tdeg = deg_of(t);
           for (int c = 0; c < cnt; ++c) {
-            const double S = Sb[c * L + t];
+            const R S = Sb[c * L + t];
             accA[r] += fA[c] * S;
             accB[r] += fB[c * (LM + 1) + tdeg] * S;
           }
@@ -965,8 +1001,8 @@ __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, co
     if (t >= L) continue;
     const int l = deg_of(t);
     const long ir = (long)j * L + t, ie = (long)(M + j) * L + t;
-    double orr = c1 * accA[r] + ycr[j * LUR + l] * mu[t];
-    double oe = c1 * accB[r] + yce[j * LUR + l] * mu[t];
+    double orr = c1 * (double)accA[r] + ycr[j * LUR + l] * (double)mu[t];
+    double oe = c1 * (double)accB[r] + yce[j * LUR + l] * (double)mu[t];
     if (base) { orr += c0 * base[ir]; oe += c0 * base[ie]; }
     out[ir] = orr;
     out[ie] = oe;
