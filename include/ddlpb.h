@@ -83,7 +83,7 @@ typedef struct {
  *   out         receives the new context
  * Defaults (change with ddlpb_set_option before the first solve): eta = 0.05,
  * FP64, restart 100, 24 Jacobi sweeps, precond_delta -1 (off),
- * max_iter 400, theta 0.5.
+ * max_iter 400, theta 0.6.
  * Errors: EINVAL, EGEOM, ENOMEM.  Device memory is allocated lazily at the
  * first solve unless a workspace is bound.
  */
@@ -119,13 +119,17 @@ void ddlpb_free(ddlpb_ctx* ctx);
  * ddlpb_set_option -- set a tuning option before the first solve (else ESTATE
  * for options that change the discrete problem: eta, precision, fmm_order).
  *   "eta"            switching width of chi_eta (Sec. 3.1), 0 < eta <= 1
- *   "precision"      0 = FP64 everywhere; 1 = mixed: FP64 iterative refinement
- *                    (FP64 residual b - L x) around GMRES solves of the correction
- *                    equation in which the near-field A/B kernels (operator and
- *                    Jacobi sweeps) compute in FP32; Krylov vectors,
- *                    orthogonalisation, norms, Bessel ratios, the FMM and the
- *                    single-layer sums stay FP64 (stats.refinements counts the
- *                    refinement steps).  Needs the cap lists (else FP64 is used).
+ *   "precision"      0 = FP64 everywhere.
+ *                    1 = mixed: the Jacobi sweeps of the preconditioner run the
+ *                    near-field A/B kernels in FP32; flexible GMRES on the FP64
+ *                    operator (FP64 residual, vectors, orthogonalisation, norms).
+ *                    2 = mixed with FP32 operator: FP64 iterative refinement (FP64
+ *                    residual b - L x) around GMRES solves of the correction
+ *                    equation in which the near-field kernels (operator and
+ *                    sweeps) compute in FP32 (stats.refinements counts the steps).
+ *                    In both, Bessel ratios, the FMM, the single-layer sums, the
+ *                    energy and the forces stay FP64.  Both need the cap lists
+ *                    (else FP64 is used).
  *   "gmres_restart"  outer Krylov subspace size (1..200)
  *   "inner_sweeps"   Jacobi sweeps on L_AB = [A 0; 0 B] used as the innermost
  *                    preconditioner (0..64; Sec. 4 uses L_AB as preconditioner)

@@ -74,7 +74,7 @@ struct ddlpb_ctx {
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
-  double theta = 0.5;
+  double theta = 0.6;
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic)
   int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
   struct M2LCfg { bool valid = false, alds = false; int nw = 0, per_cu = 0; size_t bytes = 0; } m2l_cfg[2];
@@ -333,12 +333,13 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_t3 = cv.take<double>(D);
   c->d_V = cv.take<double>((size_t)(c->restart + 1) * D);
   const bool two_level = c->pdelta >= 0.0;
-  c->d_Z = two_level ? cv.take<double>((size_t)c->restart * D) : nullptr;
+  // flexible directions: two-level preconditioner, or the FP32 sweeps of precision 1
+  c->d_Z = (two_level || c->precision == 1) ? cv.take<double>((size_t)c->restart * D) : nullptr;
   c->d_Vin = two_level ? cv.take<double>((size_t)(c->inner_iters + 1) * D) : nullptr;
   c->d_t4 = cv.take<double>(D);
   c->d_t5 = cv.take<double>(D);
-  c->d_rr = c->precision == 1 ? cv.take<double>(D) : nullptr;  // residual and correction of the mixed path
-  c->d_dd = c->precision == 1 ? cv.take<double>(D) : nullptr;
+  c->d_rr = c->precision == 2 ? cv.take<double>(D) : nullptr;  // residual and correction of the refinement
+  c->d_dd = c->precision == 2 ? cv.take<double>(D) : nullptr;
   c->d_pptr = cv.take<int>(M + 1);
   c->cap_cap = std::max(c->cap_cap, c->cap_est);
   c->d_cptr = cv.take<int>(M + 1);
@@ -628,7 +629,7 @@ void sl_field_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double*
 void sl_adjoint_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double* cgrid, int lo, int exclude_self,
                      int accumulate, int ldl, double* lam) {
   KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pairs_pts);
-  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(128), 0, c->stream, c->M, c->N,
+  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
                                      c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_ur,
                                      c->LUR, c->kappa, exclude_self, accumulate, ldl, lam));
   HIPCHK(hipGetLastError());
@@ -854,7 +855,7 @@ void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self
   if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
   {
     KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pts_fmm);
-    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(128), 0, c->stream, c->M, c->N,
+    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
                                        c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, cgrid,
                                        c->d_ur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
     HIPCHK(hipGetLastError());
@@ -1023,6 +1024,19 @@ int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b
 int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
   VecOp opL = [&](const double* in, double* out) { if (transpose) op_LT(c, in, out); else op_L(c, in, out); };
   VecOp jac = [&](const double* in, double* out) { precond(c, transpose, in, out); };
+  if (c->precision == 1 && c->use_caps && c->pdelta < 0.0) {
+    // FP32 Jacobi sweeps as the preconditioner of flexible GMRES on the FP64 operator:
+    // the sweeps are linear only up to single-precision rounding, so the
+    // preconditioned directions are stored (FGMRES) and the FP64 residual is minimised
+    VecOp jac32 = [&](const double* in, double* out) {
+      const int keep = c->cur_prec;
+      c->cur_prec = 1;
+      precond(c, transpose, in, out);
+      c->cur_prec = keep;
+    };
+    return gmres_core(c, opL, jac32, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
+                      c->d_t1, c->d_t2, iters, relres);
+  }
   if (c->pdelta < 0.0)
     return gmres_core(c, opL, jac, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, nullptr, c->d_w,
                       c->d_t1, c->d_t2, iters, relres);
@@ -1038,7 +1052,8 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
                     c->d_t1, c->d_t2, iters, relres);
 }
 
-// L x = b (or L^T x = b).  FP64: GMRES.  Mixed: FP64 iterative refinement around
+// L x = b (or L^T x = b).  Precision 0 and 1: GMRES (1: FP32 preconditioner, see
+// gmres).  Precision 2: FP64 iterative refinement around
 // GMRES solves of the correction equation with the FP32 near-field kernels (FP64
 // Krylov vectors, orthogonalisation and norms); each correction is solved to the
 // relative tolerance that would meet tol, but not below kInnerFloor, and the FP64
@@ -1050,7 +1065,7 @@ constexpr int kMaxRefine = 10;
 constexpr double kInnerFloor = 1e-4;
 int solve_system(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
   c->cur_prec = 0;
-  if (c->precision == 0 || !c->use_caps || !c->d_rr) {
+  if (c->precision != 2 || !c->use_caps || !c->d_rr) {
     c->stats.refinements = 0;
     return gmres(c, transpose, b, x, tol, iters, relres);
   }
@@ -1544,7 +1559,7 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     c->eta = v;
   } else if (k == "precision") {
     if (fixed) return DDLPB_ESTATE;
-    if (v != 0 && v != 1) return DDLPB_EINVAL;
+    if (v != 0 && v != 1 && v != 2) return DDLPB_EINVAL;
     c->precision = (int)v;
     c->stats.precision = (int)v;
   } else if (k == "gmres_restart") {

@@ -301,13 +301,8 @@ __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, c
 
 // Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
 // for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
-// One block of 128 threads per sphere j; the active points of each listed sphere are
-// taken kSlaChunk at a time: the four lanes of a point write its harmonics (columns
-// m = q mod 4) and degree weights to LDS, then one thread per coefficient
-// accumulates over the chunk (in point order: deterministic).
-constexpr int kSlaChunk = 32;
 template <int LMO>
-__global__ __launch_bounds__(128) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
+__global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
                                                           const int* __restrict__ act_n, const double* __restrict__ xyz,
                                                           const double* __restrict__ rad, const double* __restrict__ leb,
                                                           const int* __restrict__ lptr, const int* __restrict__ lidx,
@@ -315,64 +310,44 @@ __global__ __launch_bounds__(128) void k_sl_adjoint_list(int M, int N, const int
                                                           int LUR, double kappa, int exclude_self, int accumulate,
                                                           int LDL, double* __restrict__ lam) {
   constexpr int LO = (LMO + 1) * (LMO + 1);
-  constexpr int NT = (LMO + 1) * (LMO + 2) / 2;
-  constexpr int NA = (LO + 127) / 128;
-  __shared__ double Sb[kSlaChunk * LO];
-  __shared__ double fw[kSlaChunk * (LMO + 1)];
-  __shared__ double spmm[LMO + 1], sra[NT], srb[NT], siu[LMO + 1];
-  const int j = blockIdx.x;  // blockDim.x == 128
-  for (int t = threadIdx.x; t < NT; t += blockDim.x) {
-    sra[t] = c_ra[t];
-    srb[t] = c_rb[t];
-    if (t <= LMO) {
-      spmm[t] = c_pmm[t];
-      siu[t] = 1.0 / ur[j * LUR + t];
-    }
-  }
+  __shared__ double red[4 * LO];
+  const int j = blockIdx.x;
   const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
-  const int qd = threadIdx.x & 3, cl4 = threadIdx.x >> 2;
-  double acc[NA];
+  double iu[LMO + 1];
 #pragma unroll
-  for (int r = 0; r < NA; ++r) acc[r] = 0.0;
-  __syncthreads();
+  for (int l = 0; l <= LMO; ++l) iu[l] = 1.0 / ur[j * LUR + l];
+  double acc[LO];
+#pragma unroll
+  for (int t = 0; t < LO; ++t) acc[t] = 0.0;
   for (int q = lptr[j]; q < lptr[j + 1]; ++q) {
     const int i = lidx[q];
     if (exclude_self && i == j) continue;
-    const int k0 = act_ptr[i], k1 = act_ptr[i + 1];
-    for (int kb = k0; kb < k1; kb += kSlaChunk) {
-      const int cnt = min(kSlaChunk, k1 - kb);
-      if (cl4 < cnt) {
-        const int n = act_n[kb + cl4];
-        const double c = cgrid[(long)i * N + n];
-        const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-        const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-        const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
-        if (qd == 0) {
-          const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
-          double u[LMO + 1];
-          k_weights<LMO, double>(rho, kappa, u);
+    for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x) {
+      const int n = act_n[k];
+      const double c = cgrid[(long)i * N + n];
+      if (c == 0.0) continue;
+      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
+      double u[LMO + 1];
+      k_weights<LMO, double>(rho, kappa, u);
 #pragma unroll
-          for (int l = 0; l <= LMO; ++l) fw[cl4 * (LMO + 1) + l] = u[l] * c * siu[l];
-        }
-        double* Sr = Sb + cl4 * LO;
-        solid_harmonic_quad<LMO, double>(vx, vy, vz, qd, spmm, sra, srb, [&](int, int idx, double S) { Sr[idx] = S; });
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < NA; ++r) {
-        const int t = threadIdx.x + 128 * r;
-        if (t < LO) {
-          const int l = deg_of(t);
-          for (int c = 0; c < cnt; ++c) acc[r] += fw[c * (LMO + 1) + l] * Sb[c * LO + t];
-        }
-      }
-      __syncthreads();
+      for (int l = 0; l <= LMO; ++l) u[l] *= c * iu[l];
+      for_each_solid_harmonic<LMO, double>(vx, vy, vz, [&](int l, int idx, double S) { acc[idx] += u[l] * S; });
     }
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int r = 0; r < NA; ++r) {
-    const int t = threadIdx.x + 128 * r;
-    if (t < LO) lam[(long)j * LDL + t] = (accumulate ? lam[(long)j * LDL + t] : 0.0) + acc[r];
+  for (int t = 0; t < LO; ++t) {
+    double v = wave_sum(acc[t]);
+    if (lane == 0) red[wid * LO + t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < LO; t += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * LO + t];
+    lam[(long)j * LDL + t] = (accumulate ? lam[(long)j * LDL + t] : 0.0) + s;
   }
 }
 
