@@ -70,6 +70,7 @@ struct ddlpb_ctx {
   int precision = 0, restart = 100, sweeps = 24, maxit = 400, leaf = 32;
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
   double *d_rr = nullptr, *d_dd = nullptr;
+  double* d_YT = nullptr;
   bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
@@ -125,7 +126,7 @@ struct ddlpb_ctx {
   int* d_fjrow = nullptr;
   double* d_fZ[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [kernel][direction]
   int* d_fZslot[2] = {nullptr, nullptr};
-  int *d_fm2lord = nullptr, *d_fm2ltord = nullptr, *d_fctr = nullptr;
+  int *d_fm2lx = nullptr, *d_fm2ltx = nullptr, *d_fctr = nullptr;
   int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
       *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
       *d_sleaf = nullptr;
@@ -294,6 +295,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_q = cv.take<double>(M);
   c->d_leb = cv.take<double>(4 * N);
   c->d_Y = cv.take<double>(N * c->LY);
+  c->d_YT = cv.take<double>(N * c->LY);  // transposed [LY][N]: coalesced over points
   c->d_nptr = cv.take<int>(M + 1);
   c->d_nidx = cv.take<int>(std::max<size_t>(nnz, 1));
   c->d_nrev = cv.take<int>(std::max<size_t>(nnz, 1));
@@ -394,9 +396,9 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
       for (int d = 0; d < 2; ++d) c->d_fZ[k][d] = cv.take<double>(std::max<size_t>(c->tables.Z[k][d].size(), 1));
       c->d_fZslot[k] = cv.take<int>(std::max<size_t>(c->tables.Zslot[k].size(), 1));
     }
-    c->d_fm2lord = cv.take<int>(nn);
-    c->d_fm2ltord = cv.take<int>(nn);
-    c->d_fctr = cv.take<int>(64);
+    c->d_fm2lx = cv.take<int>(9);
+    c->d_fm2ltx = cv.take<int>(9);
+    c->d_fctr = cv.take<int>(8 * 32);
     c->d_Mn = cv.take<double>(nn * P);
     c->d_Ln = cv.take<double>(nn * P);
     c->d_SL = cv.take<double>(M * P);
@@ -567,7 +569,7 @@ void launch_LTZ_caps(ddlpb_ctx* c, const double* base, double c0, const double* 
       HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_LTZ_caps<LMc, R>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((k_apply_LTZ_caps<LMc, R>), dim3(c->M), dim3(128), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
-                       c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw, c->d_U, c->d_isgr,
+                       c->d_YT, c->d_leb, c->d_xyz, c->d_rad, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw, c->d_U, c->d_isgr,
                        c->d_ycr, c->d_yce, c->d_Cl, c->LUR, c->kappa, c->nterms, base, c0, zr, ze, c1, lam, llam, out);
   });
   HIPCHK(hipGetLastError());
@@ -589,8 +591,9 @@ void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, 
 }
 
 void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
-  LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_syn2<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
-                                          c->d_Y, c->d_leb, c->d_U, Z, mode, o1, o2));
+  const int nt = std::min(512, (c->N + 63) / 64 * 64);
+  LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_syn2<LMc>), dim3(c->M), dim3(nt), 0, c->stream, c->M, c->N, c->LY,
+                                          c->d_YT, c->d_leb, c->d_U, Z, mode, o1, o2));
   HIPCHK(hipGetLastError());
 }
 
@@ -735,8 +738,8 @@ void launch_m2l_fast(ddlpb_ctx* c, const FmmDev& f, const M2LTab& zt, int nw, bo
     hipLaunchKernelGGL((k_fmm_m2l_fast<NI, false>), dim3(blocks), dim3(64 * nw), bytes, c->stream, f, zt,
                        c->tree.nnodes, lptr, lidx, transposed, in, out);
 }
-__global__ void k_set_int(int* p, int v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void k_zero_ints(int* p, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
 void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx, int transposed, const double* in,
                 double* out) {
@@ -754,15 +757,15 @@ void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx,
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     c->m2l_layout = nw * (alds ? 1 : -1);
-    const int blocks = std::max(1, std::min((t.nnodes + nw - 1) / nw, ncu * std::max(per_cu, 1)));
+    const int blocks = 8 * std::max(1, ncu * std::max(per_cu, 1) / 8);  // whole rounds over the 8 groups
     M2LTab zt;
     zt.Z = c->d_fZ[f.kernel][transposed ? 1 : 0];
     zt.slot = c->d_fZslot[f.kernel];
-    zt.order = transposed ? c->d_fm2ltord : c->d_fm2lord;
+    zt.xrange = transposed ? c->d_fm2ltx : c->d_fm2lx;
     zt.counter = c->d_fctr;
     zt.nZ = (int)tb.Z[f.kernel][0].size();
     zt.nslot = tb.nslot;
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 0);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(256), 0, c->stream, c->d_fctr, 8 * 32);
     switch (NI) {
       case 1: launch_m2l_fast<1>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
       case 2: launch_m2l_fast<2>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
@@ -826,7 +829,7 @@ void l2p(ddlpb_ctx* c, int mode, double c2, double* out1, double* out2) {
   if (c->nact == 0) return;
   const int P = (c->fmm_order + 1) * (c->fmm_order + 1);
   hipLaunchKernelGGL(k_l2p, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->nact, c->N, P, c->LY, c->d_actsph,
-                     c->d_actn, c->d_rad, c->d_Y, c->d_SL, mode, c2, out1, out2);
+                     c->d_actn, c->d_rad, c->d_YT, c->d_SL, mode, c2, out1, out2);
   HIPCHK(hipGetLastError());
 }
 void p2l_dual(ddlpb_ctx* c, const double* g1, const double* g2, double* Lam) {
@@ -1150,6 +1153,10 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_q, c->q.data(), M * sizeof(double));
   up(c->d_leb, c->rule->xyzw, 4 * N * sizeof(double));
   up(c->d_Y, Y.data(), Y.size() * sizeof(double));
+  std::vector<double> YT(Y.size());
+  for (int n = 0; n < N; ++n)
+    for (int t = 0; t < c->LY; ++t) YT[(size_t)t * N + n] = Y[(size_t)n * c->LY + t];
+  up(c->d_YT, YT.data(), YT.size() * sizeof(double));
   up(c->d_nptr, c->nptr.data(), (M + 1) * sizeof(int));
   up(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int));
   up(c->d_nrev, c->nrev.data(), c->nrev.size() * sizeof(int));
@@ -1215,8 +1222,8 @@ void upload_tree(ddlpb_ctx* c) {
   up(c->d_fm2ls, t.m2l_src.data(), t.m2l_src.size() * sizeof(int));
   up(c->d_fm2ltp, t.m2lt_ptr.data(), t.m2lt_ptr.size() * sizeof(int));
   up(c->d_fm2ltt, t.m2lt_tgt.data(), t.m2lt_tgt.size() * sizeof(int));
-  up(c->d_fm2lord, t.m2l_order.data(), t.m2l_order.size() * sizeof(int));
-  up(c->d_fm2ltord, t.m2lt_order.data(), t.m2lt_order.size() * sizeof(int));
+  up(c->d_fm2lx, t.m2l_xcd.data(), t.m2l_xcd.size() * sizeof(int));
+  up(c->d_fm2ltx, t.m2lt_xcd.data(), t.m2lt_xcd.size() * sizeof(int));
   up(c->d_fnp, t.near_ptr.data(), t.near_ptr.size() * sizeof(int));
   up(c->d_fni, t.near_idx.data(), t.near_idx.size() * sizeof(int));
   hipLaunchKernelGGL(k_fmm_node_radial, dim3(nblk(t.nnodes, 128)), dim3(128), 0, c->stream, t.nnodes, c->fmm_order,

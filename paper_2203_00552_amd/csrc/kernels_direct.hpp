@@ -472,11 +472,12 @@ __global__ __launch_bounds__(256) void k_apply_LX(int M, int N, int LY, const do
 
 // ---------------------------------------------- syntheses on the grid
 // mode 0: zr = Syn(Z_r), ze = Syn(Z_e);  mode 1: c = w U Syn(Z_r + Z_e) (adjoint charges)
+// YT: harmonic table transposed, [LY][N] (consecutive threads read consecutive points)
 template <int LM>
-__global__ __launch_bounds__(256) void k_syn2(int M, int N, int LY, const double* __restrict__ Y,
-                                               const double* __restrict__ leb, const double* __restrict__ U,
-                                               const double* __restrict__ Z, int mode, double* __restrict__ o1,
-                                               double* __restrict__ o2) {
+__global__ __launch_bounds__(512) void k_syn2(int M, int N, int LY, const double* __restrict__ YT,
+                                              const double* __restrict__ leb, const double* __restrict__ U,
+                                              const double* __restrict__ Z, int mode, double* __restrict__ o1,
+                                              double* __restrict__ o2) {
   constexpr int L = (LM + 1) * (LM + 1);
   __shared__ double zr[L], ze[L];
   const int i = blockIdx.x;
@@ -486,10 +487,13 @@ __global__ __launch_bounds__(256) void k_syn2(int M, int N, int LY, const double
   }
   __syncthreads();
   for (int n = threadIdx.x; n < N; n += blockDim.x) {
-    const double* Yn = Y + (long)n * LY;
     double a = 0.0, b = 0.0;
 #pragma unroll 9
-    for (int t = 0; t < L; ++t) { a += Yn[t] * zr[t]; b += Yn[t] * ze[t]; }
+    for (int t = 0; t < L; ++t) {
+      const double y = YT[(long)t * N + n];
+      a += y * zr[t];
+      b += y * ze[t];
+    }
     if (mode == 0) {
       o1[(long)i * N + n] = a;
       o2[(long)i * N + n] = b;
@@ -741,7 +745,7 @@ __host__ __device__ constexpr size_t k_apply_LX_caps_lds_entries(int N) {
 }
 // R: compute type (double, or float on the mixed path); inputs and outputs are FP64
 template <int LM, class R>
-__global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, const double* __restrict__ Y,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_LX_caps(int M, int N, int LY, const double* __restrict__ Y,
                                                         const double* __restrict__ leb, const double* __restrict__ xyz,
                                                         const double* __restrict__ rad, const int* __restrict__ nptr,
                                                         const int* __restrict__ nidx, const int* __restrict__ cptr,
@@ -846,14 +850,46 @@ __global__ __launch_bounds__(256) void k_apply_LX_caps(int M, int N, int LY, con
       __syncthreads();
     }
   }
+  // An transforms: the point sum of every coefficient is split over kAnParts thread
+  // groups (all threads busy), partial sums combined in LDS (reusing the cap buffers)
+  constexpr int kAnParts = 3;
+  const bool grid_terms = gr1 != nullptr || ge != nullptr;  // uniform: the single-layer part
+  const int nper = (N + kAnParts - 1) / kAnParts;
+  R* part = capA;  // [kAnParts][4][L], over capA, capB and sX (no longer used)
+  static_assert(kAnParts * 4 * L <= 2 * kCapChunk + kNbrLds * 2 * L, "An partial sums exceed the cap buffers");
+  for (int u = threadIdx.x; u < kAnParts * L; u += blockDim.x) {
+    const int t = u % L, g = u / L;
+    const int n0 = g * nper, n1 = min(N, n0 + nper);
+    R sa = R(0), sb = R(0), sr = R(0), se = R(0);
+    if (grid_terms) {
+      for (int n = n0; n < n1; ++n) {
+        const R wy = R(leb[4 * n + 3] * Y[(long)n * LY + t]);
+        sa += wy * vA[n];
+        sb += wy * vB[n];
+        sr += wy * gR[n];
+        se += wy * gE[n];
+      }
+    } else {
+      for (int n = n0; n < n1; ++n) {
+        const R wy = R(leb[4 * n + 3] * Y[(long)n * LY + t]);
+        sa += wy * vA[n];
+        sb += wy * vB[n];
+      }
+    }
+    part[(g * 4 + 0) * L + t] = sa;
+    part[(g * 4 + 1) * L + t] = sb;
+    part[(g * 4 + 2) * L + t] = sr;
+    part[(g * 4 + 3) * L + t] = se;
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
     R sa = R(0), sb = R(0), sr = R(0), se = R(0);
-    for (int n = 0; n < N; ++n) {
-      const R wy = R(leb[4 * n + 3] * Y[(long)n * LY + t]);
-      sa += wy * vA[n];
-      sb += wy * vB[n];
-      sr += wy * gR[n];
-      se += wy * gE[n];
+#pragma unroll
+    for (int g = 0; g < kAnParts; ++g) {
+      sa += part[(g * 4 + 0) * L + t];
+      sb += part[(g * 4 + 1) * L + t];
+      sr += part[(g * 4 + 2) * L + t];
+      se += part[(g * 4 + 3) * L + t];
     }
     const long ir = (long)i * L + t, ie = (long)(M + i) * L + t;
     double orr = c1 * (double)sa + cg * (double)sr, oe = c1 * (double)sb + cg * (double)se;
@@ -875,6 +911,7 @@ __host__ __device__ constexpr size_t k_apply_LTZ_caps_lds_entries(int N) {
 }
 template <int LM, class R>
 __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, const double* __restrict__ Y,
+                                                         const double* __restrict__ YT,
                                                          const double* __restrict__ leb, const double* __restrict__ xyz,
                                                          const double* __restrict__ rad, const int* __restrict__ rptr,
                                                          const int* __restrict__ rc_i, const int* __restrict__ rc_n,
@@ -910,9 +947,8 @@ __global__ __launch_bounds__(128) void k_apply_LTZ_caps(int M, int N, int LY, co
     for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = R(Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t]);
     __syncthreads();
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
-      const double* Yn = Y + (long)n * LY;
       R a = R(0);
-      for (int t = 0; t < L; ++t) a += R(Yn[t]) * cl[t];
+      for (int t = 0; t < L; ++t) a += R(YT[(long)t * N + n]) * cl[t];
       gg[n] = R(U[(long)j * N + n]) * a;
     }
     __syncthreads();
