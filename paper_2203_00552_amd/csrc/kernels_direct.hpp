@@ -319,10 +319,33 @@ __global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int
   double acc[LO];
 #pragma unroll
   for (int t = 0; t < LO; ++t) acc[t] = 0.0;
-  for (int q = lptr[j]; q < lptr[j + 1]; ++q) {
-    const int i = lidx[q];
-    if (exclude_self && i == j) continue;
-    for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x) {
+  // the active points of up to kSlaSeg listed spheres are numbered consecutively
+  // (prefix sums in LDS) so that every thread of the block has points to take
+  constexpr int kSlaSeg = 128;
+  __shared__ int seg_sph[kSlaSeg], seg_pre[kSlaSeg + 1];
+  for (int q0 = lptr[j]; q0 < lptr[j + 1]; q0 += kSlaSeg) {
+    const int ns = min(kSlaSeg, lptr[j + 1] - q0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc_n = 0;
+      for (int u = 0; u < ns; ++u) {
+        const int i = lidx[q0 + u];
+        seg_sph[u] = i;
+        seg_pre[u] = acc_n;
+        acc_n += (exclude_self && i == j) ? 0 : act_ptr[i + 1] - act_ptr[i];
+      }
+      seg_pre[ns] = acc_n;
+    }
+    __syncthreads();
+    const int total = seg_pre[ns];
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+      int lo = 0, hi = ns - 1;  // last u with seg_pre[u] <= f
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
+      }
+      const int i = seg_sph[lo];
+      const int k = act_ptr[i] + (f - seg_pre[lo]);
       const int n = act_n[k];
       const double c = cgrid[(long)i * N + n];
       if (c == 0.0) continue;
