@@ -39,7 +39,8 @@ extern "C" {
 #define DDLPB_EGEOM (-2)    /* coincident sphere centres (distance < 1e-12 A) */
 #define DDLPB_ENOMEM (-3)   /* device or host allocation failed / workspace too small */
 #define DDLPB_EDEVICE (-4)  /* a HIP call failed */
-#define DDLPB_ENOCONV (-5)  /* iterative solver did not reach the tolerance in max_iter */
+#define DDLPB_ENOCONV (-5)  /* iterative solver did not reach the tolerance in max_iter, or
+                               stagnated (a restart cycle reduced the residual < 10 %) */
 #define DDLPB_ESTATE (-6)   /* call order violated (e.g. forces before adjoint) */
 
 typedef struct ddlpb_ctx ddlpb_ctx;

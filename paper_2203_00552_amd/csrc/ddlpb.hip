@@ -126,7 +126,7 @@ struct ddlpb_ctx {
   int* d_fjrow = nullptr;
   double* d_fZ[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [kernel][direction]
   int* d_fZslot[2] = {nullptr, nullptr};
-  int *d_fm2lx = nullptr, *d_fm2ltx = nullptr, *d_fctr = nullptr;
+  int *d_fm2lord = nullptr, *d_fm2ltord = nullptr, *d_fctr = nullptr;
   int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
       *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
       *d_sleaf = nullptr;
@@ -396,9 +396,9 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
       for (int d = 0; d < 2; ++d) c->d_fZ[k][d] = cv.take<double>(std::max<size_t>(c->tables.Z[k][d].size(), 1));
       c->d_fZslot[k] = cv.take<int>(std::max<size_t>(c->tables.Zslot[k].size(), 1));
     }
-    c->d_fm2lx = cv.take<int>(9);
-    c->d_fm2ltx = cv.take<int>(9);
-    c->d_fctr = cv.take<int>(8 * 32);
+    c->d_fm2lord = cv.take<int>(nn);
+    c->d_fm2ltord = cv.take<int>(nn);
+    c->d_fctr = cv.take<int>(64);
     c->d_Mn = cv.take<double>(nn * P);
     c->d_Ln = cv.take<double>(nn * P);
     c->d_SL = cv.take<double>(M * P);
@@ -757,15 +757,15 @@ void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx,
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     c->m2l_layout = nw * (alds ? 1 : -1);
-    const int blocks = 8 * std::max(1, ncu * std::max(per_cu, 1) / 8);  // whole rounds over the 8 groups
+    const int blocks = std::max(1, std::min((t.nnodes + nw - 1) / nw, ncu * std::max(per_cu, 1)));
     M2LTab zt;
     zt.Z = c->d_fZ[f.kernel][transposed ? 1 : 0];
     zt.slot = c->d_fZslot[f.kernel];
-    zt.xrange = transposed ? c->d_fm2ltx : c->d_fm2lx;
+    zt.order = transposed ? c->d_fm2ltord : c->d_fm2lord;
     zt.counter = c->d_fctr;
     zt.nZ = (int)tb.Z[f.kernel][0].size();
     zt.nslot = tb.nslot;
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(256), 0, c->stream, c->d_fctr, 8 * 32);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 1);
     switch (NI) {
       case 1: launch_m2l_fast<1>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
       case 2: launch_m2l_fast<2>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
@@ -962,9 +962,12 @@ int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b
       axpby(c, -1.0, tw, 1.0, V);
     }
     const double beta = norm2(c, V);
+    const double rel_prev = rel;
     rel = beta / bn;
     if (rel <= tol) { conv = true; break; }
     if (total >= maxit || cycles >= max_cycles) break;
+    // stagnation: a whole restart cycle that reduced the residual by less than 10 %
+    if (cycles >= 1 && m >= 20 && rel > 0.9 * rel_prev) break;
     axpby(c, 0.0, V, 1.0 / beta, V);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
@@ -1222,8 +1225,8 @@ void upload_tree(ddlpb_ctx* c) {
   up(c->d_fm2ls, t.m2l_src.data(), t.m2l_src.size() * sizeof(int));
   up(c->d_fm2ltp, t.m2lt_ptr.data(), t.m2lt_ptr.size() * sizeof(int));
   up(c->d_fm2ltt, t.m2lt_tgt.data(), t.m2lt_tgt.size() * sizeof(int));
-  up(c->d_fm2lx, t.m2l_xcd.data(), t.m2l_xcd.size() * sizeof(int));
-  up(c->d_fm2ltx, t.m2lt_xcd.data(), t.m2lt_xcd.size() * sizeof(int));
+  up(c->d_fm2lord, t.m2l_order.data(), t.m2l_order.size() * sizeof(int));
+  up(c->d_fm2ltord, t.m2lt_order.data(), t.m2lt_order.size() * sizeof(int));
   up(c->d_fnp, t.near_ptr.data(), t.near_ptr.size() * sizeof(int));
   up(c->d_fni, t.near_idx.data(), t.near_idx.size() * sizeof(int));
   hipLaunchKernelGGL(k_fmm_node_radial, dim3(nblk(t.nnodes, 128)), dim3(128), 0, c->stream, t.nnodes, c->fmm_order,

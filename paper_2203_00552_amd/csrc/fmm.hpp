@@ -334,8 +334,8 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __r
 //   * the first rotation is fused with the load of the input expansion and the last
 //     one with the accumulation, which stays in registers; the next source of the
 //     list is fetched into registers while the current one is translated;
-//   * wavefronts take target nodes from per-group counters over contiguous node
-//     ranges (tree order), one group per XCD.
+//   * wavefronts take target nodes from a counter in the order given by `order`
+//     (longest lists first).
 // LDS: the tables (shared by the block) followed by one scratch area per wavefront.
 __device__ __forceinline__ double ipow_d(double b, int e) {
   double r = 1.0;
@@ -397,10 +397,10 @@ __device__ __forceinline__ void zrot_alt(double* b, int P, const double* c, cons
 
 // z-translation table of one M2L launch (kernel type and direction)
 struct M2LTab {
-  const double* Z;   // entries, see the host tables
-  const int* slot;   // [nslot][2]: lo << 8 | |m| (or -1), offset
-  const int* xrange; // [9]: node ranges of the 8 block groups (tree order)
-  int* counter;      // [8 * 32]: one work counter per group (128-byte apart), zero at launch
+  const double* Z;  // entries, see the host tables
+  const int* slot;  // [nslot][2]: lo << 8 | |m| (or -1), offset
+  const int* order; // target node order (longest lists first)
+  int* counter;     // work counter, zero at launch
   int nZ, nslot;
 };
 
@@ -450,17 +450,12 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
     lpack |= (l & 63) << (6 * i);
   }
 
-  // Blocks are dealt to the XCDs round-robin: group g = blockIdx mod 8 takes the
-  // nodes of one contiguous stretch of the tree, so sources shared by nearby targets
-  // stay in that XCD's L2.
-  const int g = blockIdx.x & 7;
-  const int nbeg = zt.xrange[g], nend = zt.xrange[g + 1];
   for (;;) {
     int k = 0;
-    if (lane == 0) k = atomicAdd(zt.counter + 32 * g, 1);
+    if (lane == 0) k = atomicAdd(zt.counter, 1);
     k = __builtin_amdgcn_readfirstlane(__shfl(k, 0));
-    if (nbeg + k >= nend) break;
-    const int n = nbeg + k;
+    if (k >= nn) break;
+    const int n = zt.order[k];
     const int q0 = lptr[n], q1 = lptr[n + 1];
     double acc[NI];
 #pragma unroll

@@ -34,9 +34,7 @@ struct Tree {
   std::vector<int> m2l_ptr, m2l_src;  // per target node, source nodes (sorted)
   std::vector<int> m2lt_ptr, m2lt_tgt;  // transposed: per source node, target nodes
   std::vector<int> near_ptr, near_idx;  // per target sphere, source spheres (self included)
-  // M2L work split for the 8 XCDs: node ranges [xcd[g], xcd[g+1]) in tree (depth-first)
-  // order with about equal numbers of translations, per list direction
-  std::vector<int> m2l_xcd, m2lt_xcd;
+  std::vector<int> m2l_order, m2lt_order;  // nodes by decreasing list length (work order)
 };
 
 inline void build_tree(int M, const double* x, const double* r, Tree& t) {
@@ -141,17 +139,14 @@ inline void build_lists(int M, const double* r, double theta, Tree& t) {
     t.m2lt_tgt.insert(t.m2lt_tgt.end(), m2lt[n].begin(), m2lt[n].end());
     t.m2lt_ptr[n + 1] = (int)t.m2lt_tgt.size();
   }
-  auto split = [&](const std::vector<int>& ptr, std::vector<int>& x) {
-    const int G = 8;
-    x.assign(G + 1, t.nnodes);
-    x[0] = 0;
-    const double total = (double)ptr[t.nnodes];
-    int g = 1;
-    for (int n = 0; n < t.nnodes && g < G; ++n)
-      while (g < G && ptr[n + 1] >= total * g / G) x[g++] = n + 1;
+  auto by_length = [&](const std::vector<int>& ptr, std::vector<int>& ord) {
+    ord.resize(t.nnodes);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
   };
-  split(t.m2l_ptr, t.m2l_xcd);
-  split(t.m2lt_ptr, t.m2lt_xcd);
+  by_length(t.m2l_ptr, t.m2l_order);
+  by_length(t.m2lt_ptr, t.m2lt_order);
   t.near_ptr.assign(M + 1, 0);
   t.near_idx.clear();
   for (int i = 0; i < M; ++i) {
