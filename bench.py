@@ -22,6 +22,23 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (= matrix) peak
 PRECISION = {"fp64": 0, "mixed": 1, "mixed-refine": 2}
 
 
+def measured_traffic(kernel, atoms):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/), if it was taken on this workload with the current kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2203_00552_amd", "csrc", "fmm.hpp")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("traffic_bytes_per_launch:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[2:])
+            if (line.split()[1] == kernel and int(kv["atoms"]) == atoms and kv["fmm_hpp_sha1"] == sha):
+                return float(kv["bytes"])
+    return None
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -41,7 +58,7 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-atoms", type=int, default=60)
+    p.add_argument("--cpu-sample-atoms", type=int, default=100)
     p.add_argument("--serve-requests", type=int, default=64,
                    help="requests of the serving run (0: skip); the full workload has 512")
     p.add_argument("--serve-slots", type=int, default=4)
@@ -153,7 +170,9 @@ def main():
                    "precision": args.precision, "tol": args.tol,
                    "options": {kv.split("=")[0]: float(kv.split("=")[1]) for kv in args.option}},
         "roofline": {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "launches_per_step": nl / args.steps,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(name, atoms) if args.precision == "fp64" else None,
+                     "launches_per_step": nl / args.steps,
                      "kernel_ms_per_step": ms / args.steps},
         "energy": E, "iters": [st["iters_primal"], st["iters_adjoint"]],
         "phase_ms": {k: st[k] for k in ("ms_rhs", "ms_primal", "ms_adjoint", "ms_forces")},
