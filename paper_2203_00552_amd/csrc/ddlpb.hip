@@ -3,6 +3,7 @@
 // Call order (Sec. 3.1, final summary of the force computation): ddlpb_setup ->
 // ddlpb_solve (primal L X = g) -> ddlpb_adjoint (L^T X_adj = Q) -> ddlpb_forces.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -14,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -36,6 +38,11 @@ struct HipError {
   do {                                             \
     hipError_t err__ = (x);                        \
     if (err__ != hipSuccess) throw HipError{err__}; \
+  } while (0)
+#define BLASCHK(x)                                                            \
+  do {                                                                        \
+    rocblas_status st__ = (x);                                                \
+    if (st__ != rocblas_status_success) throw HipError{hipErrorUnknown};      \
   } while (0)
 
 // One-time upload of the Legendre recurrence constants per device.
@@ -71,6 +78,9 @@ struct ddlpb_ctx {
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
   double *d_rr = nullptr, *d_dd = nullptr;
   double* d_YT = nullptr;
+  double* d_WY = nullptr;     // w_n Y_lm(s_n), [N][L] (column-major L x N): the An projection as a GEMM
+  double* d_Vpt = nullptr;    // point values of the A/B sums, [2M][N], input of the An GEMM
+  rocblas_handle blas = nullptr;
   bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
@@ -296,6 +306,8 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_leb = cv.take<double>(4 * N);
   c->d_Y = cv.take<double>(N * c->LY);
   c->d_YT = cv.take<double>(N * c->LY);  // transposed [LY][N]: coalesced over points
+  c->d_WY = cv.take<double>((size_t)N * c->L);
+  c->d_Vpt = cv.take<double>(2 * MN);
   c->d_nptr = cv.take<int>(M + 1);
   c->d_nidx = cv.take<int>(std::max<size_t>(nnz, 1));
   c->d_nrev = cv.take<int>(std::max<size_t>(nnz, 1));
@@ -319,8 +331,8 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_e = cv.take<double>(MN);
   c->d_Phi = cv.take<double>(MN);
   c->d_h = cv.take<double>(MN);
-  c->d_zr = cv.take<double>(MN);
-  c->d_ze = cv.take<double>(MN);
+  c->d_zr = cv.take<double>(2 * MN);  // zr and ze adjacent: [2M][N], output of the Syn GEMM
+  c->d_ze = c->d_zr + MN;
   c->d_cg = cv.take<double>(MN);
   c->d_eta = cv.take<double>(MN);
   c->d_xr = cv.take<double>(MN);
@@ -503,6 +515,11 @@ inline double flops_sl_pair(int lm) { double L = (lm + 1.0) * (lm + 1.0); return
 // the i_l weights (two series of nterms terms and the downward recurrence)
 inline double flops_cap_pair(int lm, int nterms) { double L = (lm + 1.0) * (lm + 1.0); return 7.0 * L + 6.0 * nterms + 8.0 * (lm + 1) + 30.0; }
 
+rocblas_handle blas(ddlpb_ctx* c) {
+  if (!c->blas) BLASCHK(rocblas_create_handle(&c->blas));
+  BLASCHK(rocblas_set_stream(c->blas, c->stream));
+  return c->blas;
+}
 void fill(ddlpb_ctx* c, double* p, long n, double v) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, c->stream, n, v, p);
@@ -548,6 +565,7 @@ void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, dou
 template <class R>
 void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
                     const double* gr2, const double* ge, double cg, double* out) {
+  const bool gemm = std::is_same<R, double>::value;  // FP64: An transforms as one GEMM
   LM_DISPATCH(c->lmax, {
     const size_t lds = k_apply_LX_caps_lds_entries<LMc>(c->N) * sizeof(R);
     if (lds > 65536)
@@ -556,9 +574,23 @@ void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* n
     hipLaunchKernelGGL((k_apply_LX_caps<LMc, R>), dim3(c->M), dim3(256), lds, c->stream, c->M, c->N, c->LY, c->d_Y,
                        c->d_leb, c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_cptr, c->d_capn, c->d_capslot,
                        c->d_capw, c->d_pcp, c->d_U, c->d_isgr, c->LUR, c->kappa, c->nterms, base, c0, nearX, c1, gr1,
-                       gr2, ge, cg, out);
+                       gr2, ge, cg, out, gemm ? c->d_Vpt : nullptr);
   });
   HIPCHK(hipGetLastError());
+  if (!gemm) return;
+  // out = c0 base + An(point values): (L x 2M) = WY (L x N) x Vpt (N x 2M), column-major
+  const long D = 2L * c->M * c->L;
+  double beta = 0.0;
+  if (base == out) {
+    beta = c0;
+  } else if (base) {
+    hipLaunchKernelGGL(k_scale, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, c0, base, out);
+    HIPCHK(hipGetLastError());
+    beta = 1.0;
+  }
+  const double one = 1.0;
+  BLASCHK(rocblas_dgemm(blas(c), rocblas_operation_none, rocblas_operation_none, c->L, 2 * c->M, c->N, &one, c->d_WY,
+                        c->L, c->d_Vpt, c->N, &beta, out, c->L));
 }
 template <class R>
 void launch_LTZ_caps(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
@@ -591,6 +623,15 @@ void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, 
 }
 
 void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
+  if (mode == 0 && o1 == c->d_zr && o2 == c->d_ze) {
+    // Syn of every sphere at once: [2M][N] = Z [2M][L] x Y^T, one DGEMM (column-major:
+    // (N x 2M) = Y(L x N, lda LY)^T (L x 2M))
+    KScope ks(c, "syn_gemm", 2.0 * c->N * c->L * 2.0 * c->M);
+    const double one = 1.0, zero = 0.0;
+    BLASCHK(rocblas_dgemm(blas(c), rocblas_operation_transpose, rocblas_operation_none, c->N, 2 * c->M, c->L, &one,
+                          c->d_Y, c->LY, Z, c->L, &zero, c->d_zr, c->N));
+    return;
+  }
   const int nt = std::min(512, (c->N + 63) / 64 * 64);
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_syn2<LMc>), dim3(c->M), dim3(nt), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_YT, c->d_leb, c->d_U, Z, mode, o1, o2));
@@ -1160,6 +1201,10 @@ void upload_and_init(ddlpb_ctx* c) {
   for (int n = 0; n < N; ++n)
     for (int t = 0; t < c->LY; ++t) YT[(size_t)t * N + n] = Y[(size_t)n * c->LY + t];
   up(c->d_YT, YT.data(), YT.size() * sizeof(double));
+  std::vector<double> WY((size_t)N * c->L);
+  for (int n = 0; n < N; ++n)
+    for (int t = 0; t < c->L; ++t) WY[(size_t)n * c->L + t] = c->rule->xyzw[4 * n + 3] * Y[(size_t)n * c->LY + t];
+  up(c->d_WY, WY.data(), WY.size() * sizeof(double));
   up(c->d_nptr, c->nptr.data(), (M + 1) * sizeof(int));
   up(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int));
   up(c->d_nrev, c->nrev.data(), c->nrev.size() * sizeof(int));
@@ -1553,6 +1598,7 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
 
 void ddlpb_free(ddlpb_ctx* c) {
   if (!c) return;
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->ws_owned && c->ws) (void)hipFree(c->ws);
   for (auto& p : c->ev_pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -652,6 +652,10 @@ __global__ void k_mupdate(long D, int nv, const double* __restrict__ V, long ldv
   w[k] = s;
 }
 // y = a x + b y
+__global__ void k_scale(long D, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k < D) y[k] = a * x[k];
+}
 __global__ void k_axpby(long D, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (k < D) y[k] = a * x[k] + b * y[k];
@@ -780,7 +784,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                         const double* __restrict__ nearX, double c1,
                                                         const double* __restrict__ gr1, const double* __restrict__ gr2,
                                                         const double* __restrict__ ge, double cg,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, double* __restrict__ Vpt) {
   constexpr int L = (LM + 1) * (LM + 1);
   constexpr int NT = (LM + 1) * (LM + 2) / 2;
   extern __shared__ double sh_raw[];
@@ -872,6 +876,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       __syncthreads();
     }
+  }
+  if (Vpt) {
+    // point values only: the An transforms of all spheres are one GEMM on the host side
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      Vpt[(long)i * N + n] = c1 * (double)vA[n] + cg * (double)gR[n];
+      Vpt[(long)(M + i) * N + n] = c1 * (double)vB[n] + cg * (double)gE[n];
+    }
+    return;
   }
   // An transforms: the point sum of every coefficient is split over kAnParts thread
   // groups (all threads busy), partial sums combined in LDS (reusing the cap buffers)
