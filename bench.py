@@ -61,7 +61,9 @@ def parse():
     p.add_argument("--cpu-sample-atoms", type=int, default=100)
     p.add_argument("--serve-requests", type=int, default=64,
                    help="requests of the serving run (0: skip); the full workload has 512")
-    p.add_argument("--serve-slots", type=int, default=4)
+    p.add_argument("--serve-slots", type=int, default=8)
+    p.add_argument("--serve-precision", choices=["fp64", "mixed", "mixed-refine"], default="mixed",
+                   help="precision of the serving requests (the serving workload is specified in mixed precision)")
     p.add_argument("--option", action="append", default=[], metavar="KEY=VALUE",
                    help="extra context option (ddlpb_set_option), repeatable")
     return p.parse_args()
@@ -95,14 +97,14 @@ def serving(args):
     for k, sp in enumerate(spec):
         x, r, q = inputs.lattice_cluster(sp["n"], seed=sp["seed"])
         reqs.append(Request(x, r, q, lmax=sp["lmax"], n_lebedev=sp["n_lebedev"], tol=1e-6,
-                            precision=PRECISION[args.precision], rid=k))
+                            precision=PRECISION[args.serve_precision], rid=k))
         times.append(sp["t"])
     server = Server(slots=args.serve_slots)
     res, span = run_arrivals(server, reqs, times)
     server.close()
     out = latency_summary(res, span)
     out.update({"slots": args.serve_slots, "max_in_flight": server.max_in_flight, "rate_per_s": 200.0,
-                "precision": args.precision, "sizes": "log-uniform [50, 20000] atoms"})
+                "precision": args.serve_precision, "sizes": "log-uniform [50, 20000] atoms"})
     return out
 
 
