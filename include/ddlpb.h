@@ -113,6 +113,17 @@ int ddlpb_adjoint(ddlpb_ctx* ctx, double tol);
  */
 int ddlpb_forces(ddlpb_ctx* ctx, double* forces_out);
 
+/*
+ * ddlpb_charge_gradient -- dE_s/dq_k for every atom, written to dedq_out [M]
+ * (host, e/Angstrom).  The adjoint solution gives the derivative with respect to
+ * any parameter of the system at no further solve (Sec. 3, adjoint method):
+ * dE/dq_k = 1/2 X_r,k00 / sqrt(4 pi) + 1/2 <X_adj, dg/dq_k>, where g depends on
+ * q_k through psi_0 and d_n psi_0 at the grid points.  Since E is quadratic in q,
+ * sum_k q_k dE/dq_k = 2 E.  Requires a prior ddlpb_adjoint (else ESTATE).
+ * Errors: EINVAL, ESTATE, EDEVICE.
+ */
+int ddlpb_charge_gradient(ddlpb_ctx* ctx, double* dedq_out);
+
 /* ddlpb_free -- release the context and any device memory it allocated. NULL is a no-op. */
 void ddlpb_free(ddlpb_ctx* ctx);
 

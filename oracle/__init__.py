@@ -159,6 +159,24 @@ class Problem:
         _load().oracle_forces_from(*self._args(), _ptr(X), _ptr(Xa), _ptr(F))
         return F
 
+    def charge_gradient(self, method="auto", tol=1e-12):
+        """dE/dq_k for every atom.  E is a quadratic form in the charges (g and Q are
+        linear in q, Sec. 2.2 and 3), so the central difference with unit step,
+        (E(q + e_k) - E(q - e_k)) / 2, is its derivative exactly (up to rounding)."""
+        out = np.zeros(self.M)
+        q0 = self.q.copy()
+        try:
+            for k in range(self.M):
+                e = []
+                for sgn in (1.0, -1.0):
+                    self.q = q0.copy()
+                    self.q[k] += sgn
+                    e.append(self.solve(method, tol=tol, forces=False)["energy"])
+                out[k] = 0.5 * (e[0] - e[1])
+        finally:
+            self.q = q0
+        return out
+
     def energy_complex_step(self, atom, coord, h=1e-30):
         """dE/dx_{atom,coord} by the complex step Im E(x + i h e)/h (dense path)."""
         d = ctypes.c_double(0.0)

@@ -17,7 +17,7 @@ ERRORS = {0: "ok", -1: "EINVAL", -2: "EGEOM", -3: "ENOMEM", -4: "EDEVICE", -5: "
 EXPORTS = ["ddlpb_setup", "ddlpb_solve", "ddlpb_adjoint", "ddlpb_forces", "ddlpb_free", "ddlpb_set_option",
            "ddlpb_update_centers", "ddlpb_workspace_bytes", "ddlpb_bind_workspace", "ddlpb_set_stream",
            "ddlpb_get_stats", "ddlpb_strerror", "ddlpb_get_grid", "ddlpb_get_solution", "ddlpb_get_rhs",
-           "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset"]
+           "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset", "ddlpb_charge_gradient"]
 
 
 class DDLPBError(RuntimeError):
@@ -56,6 +56,7 @@ def load():
         lib.ddlpb_solve.argtypes = [c_void_p, c_double, _dp]
         lib.ddlpb_adjoint.argtypes = [c_void_p, c_double]
         lib.ddlpb_forces.argtypes = [c_void_p, _dp]
+        lib.ddlpb_charge_gradient.argtypes = [c_void_p, _dp]
         lib.ddlpb_free.argtypes = [c_void_p]
         lib.ddlpb_free.restype = None
         lib.ddlpb_set_option.argtypes = [c_void_p, ctypes.c_char_p, c_double]
@@ -148,6 +149,12 @@ class Context:
         F = np.zeros((self.M, 3))
         check(load().ddlpb_forces(self._h, ptr(F)), "ddlpb_forces")
         return F
+
+    def charge_gradient(self):
+        """dE/dq_k [M] from the adjoint solution (needs a prior adjoint)."""
+        g = np.zeros(self.M)
+        check(load().ddlpb_charge_gradient(self._h, ptr(g)), "ddlpb_charge_gradient")
+        return g
 
     def update_centers(self, centers):
         x = np.ascontiguousarray(centers, dtype=np.float64).reshape(self.M, 3)

@@ -1596,6 +1596,47 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
   });
 }
 
+int ddlpb_charge_gradient(ddlpb_ctx* c, double* dedq_out) {
+  if (!c || !dedq_out) return DDLPB_EINVAL;
+  if (c->state < 2) return DDLPB_ESTATE;
+  return guarded([&]() -> int {
+    const int M = c->M, N = c->N;
+    // xi_r, grid charges, lambda' and eta: the adjoint fields of the force assembly
+    syn2(c, c->d_Xa, 0, c->d_xr, c->d_xe);
+    syn2(c, c->d_Xa, 1, c->d_cg, nullptr);
+    sl_adjoint_full(c, c->d_cg, c->lmax + 1, 1, c->LP, c->d_lam);
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eta<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->LY, c->d_Y,
+                                            c->d_cg, c->d_lam, c->LP, c->d_Cl, c->LUR, c->d_eta));
+    HIPCHK(hipGetLastError());
+    double* dq = c->d_tmp4 ? c->d_tmp4 : c->d_F;  // [M] (forces buffer when no FMM scratch)
+    const double* Mu = nullptr;
+    if (c->fmm_order == 0) {
+      if (c->nact > 0)
+        hipLaunchKernelGGL(k_dq_laplace_source, dim3(M), dim3(256), 0, c->stream, M, N, c->nact, c->d_actsph,
+                           c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta, dq);
+      else
+        fill(c, dq, M, 0.0);
+    } else {
+      hipLaunchKernelGGL(k_dq_laplace_source_list, dim3(M), dim3(256), 0, c->stream, N, c->d_actptr, c->d_actn,
+                         c->d_xyz, c->d_rad, c->d_leb, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta, c->d_fnp, c->d_fni,
+                         dq);
+      hipLaunchKernelGGL(k_lap_src_grids, dim3(nblk((long)M * N, 256)), dim3(256), 0, c->stream, M, N, c->d_leb,
+                         c->d_U, c->d_xr, c->d_eta, c->eps1, c->eps2, c->d_zr, c->d_ze);
+      HIPCHK(hipGetLastError());
+      p2l_dual(c, c->d_zr, c->d_ze, c->d_Lam);
+      fmm_transpose(c, 1, c->d_Lam, 0, 1, 0, c->d_F);  // Mu_k[0] in the forces buffer
+      Mu = c->d_F;
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_dq_final, dim3(nblk(M, 256)), dim3(256), 0, c->stream, M, c->L, c->d_X, c->d_rad, Mu, 1, dq);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(dedq_out, dq, (size_t)M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ktimer_flush(c);
+    return DDLPB_OK;
+  });
+}
+
 void ddlpb_free(ddlpb_ctx* c) {
   if (!c) return;
   if (c->blas) (void)rocblas_destroy_handle(c->blas);

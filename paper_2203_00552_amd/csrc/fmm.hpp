@@ -875,6 +875,51 @@ __global__ void k_lap_src_grids(int M, int N, const double* __restrict__ leb, co
   g2[g] = c * etag[g] / eps2;
 }
 
+// Near part of the charge derivative S_k (see k_dq_laplace_source): active points of the
+// spheres in the near list of k (symmetric lists, k itself included).
+__global__ __launch_bounds__(256) void k_dq_laplace_source_list(int N, const int* __restrict__ act_ptr,
+                                                                const int* __restrict__ act_n,
+                                                                const double* __restrict__ xyz,
+                                                                const double* __restrict__ rad,
+                                                                const double* __restrict__ leb, double eps1,
+                                                                double eps2, const double* __restrict__ U,
+                                                                const double* __restrict__ xr,
+                                                                const double* __restrict__ etag,
+                                                                const int* __restrict__ lptr,
+                                                                const int* __restrict__ lidx, double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int kq = blockIdx.x;
+  const double xk = xyz[3 * kq], yk = xyz[3 * kq + 1], zk = xyz[3 * kq + 2];
+  double acc = 0.0;
+  for (int t = lptr[kq]; t < lptr[kq + 1]; ++t) {
+    const int i = lidx[t];
+    for (int kk = act_ptr[i] + threadIdx.x; kk < act_ptr[i + 1]; kk += blockDim.x) {
+      const int n = act_n[kk];
+      const long in = (long)i * N + n;
+      const double c = -0.5 * leb[4 * n + 3] * U[in];
+      const double a1 = c * xr[in] / eps1, a2 = c * etag[in] / eps2;
+      const double s0 = leb[4 * n], s1 = leb[4 * n + 1], s2 = leb[4 * n + 2];
+      const double v0 = xyz[3 * i] + rad[i] * s0 - xk, v1 = xyz[3 * i + 1] + rad[i] * s1 - yk,
+                   v2 = xyz[3 * i + 2] + rad[i] * s2 - zk;
+      const double id = 1.0 / sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+      acc += a1 * id - a2 * (v0 * s0 + v1 * s1 + v2 * s2) * id * id * id;
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[kq] = s;
+}
+// dE/dq_k = 1/2 X_r,k00 / sqrt(4 pi) + S_k (near) + far part: the transposed Laplace FMM
+// of the weights gives the dual of each charge's degree-0 source coefficient
+// q sqrt(4 pi) / r_k (Mu_k[0]); Mu = nullptr in direct mode.
+__global__ void k_dq_final(int M, int L, const double* __restrict__ X, const double* __restrict__ rad,
+                           const double* __restrict__ Mu, int ldm, double* __restrict__ dq) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double v = dq[k] + 0.5 * X[(long)k * L] * 0.28209479177387814;  // 1/sqrt(4 pi)
+  if (Mu) v += Mu[(long)k * ldm] * 3.5449077018110318 / rad[k];  // sqrt(4 pi)
+  dq[k] = v;
+}
+
 // Far Laplace source terms from the adjoint multipoles at the charges (degree >= 1):
 // grad_{x_k} += q_k sqrt(4 pi/3)/r_k^2 (Mu_k[1,1], Mu_k[1,-1], Mu_k[1,0])
 __global__ void k_force_lap_far_source(int M, int ldm, const double* __restrict__ q, const double* __restrict__ rad,

@@ -228,6 +228,39 @@ __global__ __launch_bounds__(256) void k_force_laplace_source(int M, int N, int 
   }
 }
 
+// Charge derivative of 1/2 <X_adj, g> (Sec. 3: the adjoint solution differentiates the
+// energy with respect to any parameter of the right-hand side): g depends on q_k through
+// psi_0 and d_n psi_0 at the grid points, so
+//   S_k = sum_p a1_p / |p - x_k| - a2_p ((p - x_k) . s_p) / |p - x_k|^3,
+//   a1 = -1/2 w U xi_r / eps1,  a2 = -1/2 w U eta / eps2,
+// over every active point p (the sphere of k included).  Direct sums, one block per atom.
+__global__ __launch_bounds__(256) void k_dq_laplace_source(int M, int N, int nact, const int* __restrict__ act_sph,
+                                                           const int* __restrict__ act_n,
+                                                           const double* __restrict__ xyz,
+                                                           const double* __restrict__ rad,
+                                                           const double* __restrict__ leb, double eps1, double eps2,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ xr,
+                                                           const double* __restrict__ etag, double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int kq = blockIdx.x;
+  const double xk = xyz[3 * kq], yk = xyz[3 * kq + 1], zk = xyz[3 * kq + 2];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nact; k += blockDim.x) {
+    const int i = act_sph[k], n = act_n[k];
+    const long in = (long)i * N + n;
+    const double c = -0.5 * leb[4 * n + 3] * U[in];
+    const double a1 = c * xr[in] / eps1, a2 = c * etag[in] / eps2;
+    const double s0 = leb[4 * n], s1 = leb[4 * n + 1], s2 = leb[4 * n + 2];
+    const double v0 = xyz[3 * i] + rad[i] * s0 - xk, v1 = xyz[3 * i + 1] + rad[i] * s1 - yk,
+                 v2 = xyz[3 * i + 2] + rad[i] * s2 - zk;
+    const double id = 1.0 / sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    acc += a1 * id - a2 * (v0 * s0 + v1 * s1 + v2 * s2) * id * id * id;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[kq] = s;
+}
+
 // Source-side single-layer term: 1/2 sum_lm m_jlm sum_l'm' kappa d[a][lm][l'm'] k_l'(kappa r_j)/k_l(kappa r_j) lambda'_jl'm'
 // with lambda' the adjoint field of the grid charges c = w U xi_s on the other spheres, degree lmax+1.
 template <int LM>

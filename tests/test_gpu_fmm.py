@@ -114,3 +114,23 @@ def test_fmm_forces_match_direct_gpu():
     Ff = f.forces()
     assert abs(Ef / Ed - 1) < 1e-6
     assert _rel(Ff, Fd) < 1e-4
+
+
+def test_fmm_charge_gradient():
+    """dE/dq with the FMM (near list + transposed Laplace FMM) against the direct GPU
+    path (itself checked against the oracle in test_gpu_parity), and Euler's identity
+    sum q dE/dq = 2E at 2,000 atoms."""
+    x, r, q = inputs.lattice_cluster(400, seed=5)
+    out = []
+    for p in (0, 12):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=p)
+        f.solve(1e-11)
+        f.adjoint(1e-11)
+        out.append(f.charge_gradient())
+    assert _rel(out[1], out[0]) < 1e-6
+    x, r, q = inputs.lattice_cluster(2000, seed=6)
+    f = Context(x, r, q, lmax=8, n_lebedev=302, fmm_order=12)
+    E = f.solve(1e-10)
+    f.adjoint(1e-10)
+    g = f.charge_gradient()
+    assert abs((q * g).sum() / (2 * E) - 1) < 1e-7

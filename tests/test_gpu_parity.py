@@ -108,3 +108,17 @@ def test_apply_dense_overlaps_lmax8():
         assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max(), tr
     _, _, nn = P.grid_fields()
     assert nn.max() > 16 and ctx.stats()["n_cap_pairs"] > 512 * len(r) // 4
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_charge_gradient_config1(seed):
+    """dE/dq from the adjoint solution against the oracle's exact quadratic-form
+    difference (12 atoms, lmax 6, 110 points, direct sums)."""
+    x, r, q = inputs.small_cluster(seed)
+    ctx, P = _pair(x, r, q, 6, 110)
+    E = ctx.solve(TOL)
+    ctx.adjoint(TOL)
+    g = ctx.charge_gradient()
+    ref = P.charge_gradient("dense")
+    assert np.abs(g - ref).max() < 1e-8 * np.abs(ref).max()
+    assert abs((q * g).sum() / (2 * E) - 1) < 1e-9

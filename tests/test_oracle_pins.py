@@ -281,3 +281,33 @@ def test_octahedral_invariance(perm, signs):
     b = oracle.Problem(x @ A.T, r, q, lmax=6, n_lebedev=110).solve("dense")
     assert abs(a["energy"] - b["energy"]) < 1e-12 * abs(a["energy"])
     assert np.abs(a["forces"] @ A.T - b["forces"]).max() < 1e-10 * np.abs(a["forces"]).max()
+
+
+# ---------------------------------------------------------------- charge gradient
+def test_charge_gradient_single_sphere_closed_form():
+    """One sphere with a central charge: E = q^2/(2a) (1/(eps2 (1 + kappa a)) - 1/eps1),
+    so dE/dq = 2E/q."""
+    a, q, kap = 1.7, 0.8, 0.104
+    P = oracle.Problem([[0.3, 0.1, -0.2]], [a], [q], kappa=kap, lmax=4, n_lebedev=110)
+    g = P.charge_gradient("dense")
+    ref = q / a * (1 / (78.54 * (1 + kap * a)) - 1.0)
+    assert abs(g[0] / ref - 1) < 1e-12
+
+
+def test_charge_gradient_euler_and_small_step():
+    """Euler's identity for the quadratic form (sum q_k dE/dq_k = 2E) and agreement of
+    the unit-step difference with a small-step one (which fails unless E is quadratic)."""
+    x, r, q = inputs.small_cluster(2)
+    P = oracle.Problem(x, r, q, lmax=4, n_lebedev=50)
+    g = P.charge_gradient("dense")
+    E = P.solve("dense", forces=False)["energy"]
+    assert abs((q * g).sum() / (2 * E) - 1) < 1e-12
+    q0 = P.q.copy()
+    h = 1e-3
+    for k in (0, 5):
+        P.q = q0.copy(); P.q[k] += h
+        ep = P.solve("dense", forces=False)["energy"]
+        P.q = q0.copy(); P.q[k] -= h
+        em = P.solve("dense", forces=False)["energy"]
+        P.q = q0
+        assert abs((ep - em) / (2 * h) - g[k]) < 1e-9 * np.abs(g).max()
