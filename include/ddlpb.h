@@ -83,8 +83,9 @@ typedef struct {
  *               adjoint field at degree lmax+1
  *   out         receives the new context
  * Defaults (change with ddlpb_set_option before the first solve): eta = 0.05,
- * FP64, restart 100, 24 Jacobi sweeps, precond_delta -1 (off),
- * max_iter 400, theta 0.6.
+ * FP64, restart 100, preconditioner = 6 GMRES steps on L_AB each preconditioned
+ * by 1 Jacobi sweep (flexible outer GMRES), precond_delta -1 (off), max_iter 400,
+ * theta 0.6.
  * Errors: EINVAL, EGEOM, ENOMEM.  Device memory is allocated lazily at the
  * first solve unless a workspace is bound.
  */
@@ -145,11 +146,14 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "gmres_restart"  outer Krylov subspace size (1..200)
  *   "inner_sweeps"   Jacobi sweeps on L_AB = [A 0; 0 B] used as the innermost
  *                    preconditioner (0..64; Sec. 4 uses L_AB as preconditioner)
+ *   "precond_krylov" k > 0: the preconditioner is k GMRES steps on L_AB, each
+ *                    preconditioned by the inner_sweeps Jacobi sweeps, and the
+ *                    outer method is flexible GMRES (0..64, default 6);
+ *                    0: the sweeps alone (then 24 sweeps is a good choice)
  *   "precond_delta"  two-level preconditioner: each outer (flexible) GMRES step
  *                    is preconditioned by inner GMRES steps on P = L_AB + the
  *                    single-layer blocks of sphere pairs with |x_i - x_j| <
  *                    r_i + r_j + delta (Angstrom); < 0 (default) disables it
- *                    (then plain GMRES preconditioned by the L_AB sweeps)
  *   "inner_iters"    inner GMRES steps on P per outer step (1..200, default 12)
  *   "max_iter"       maximal GMRES iterations per solve
  *   "leaf_size"      maximal spheres per FMM tree leaf

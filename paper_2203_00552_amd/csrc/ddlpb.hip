@@ -74,7 +74,7 @@ struct ddlpb_ctx {
   std::vector<double> x, r, q;
   const ddlpb_tables::LebedevRule* rule = nullptr;
   // ---- options
-  int precision = 0, restart = 100, sweeps = 24, maxit = 400, leaf = 32;
+  int precision = 0, restart = 100, sweeps = 1, maxit = 400, leaf = 32;
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
   double *d_rr = nullptr, *d_dd = nullptr;
   double* d_YT = nullptr;
@@ -82,6 +82,7 @@ struct ddlpb_ctx {
   double* d_Vpt = nullptr;    // point values of the A/B sums, [2M][N], input of the An GEMM
   rocblas_handle blas = nullptr;
   bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
+  int pkrylov = 6;            // > 0: preconditioner = this many GMRES steps on L_AB (flexible outer)
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
@@ -347,9 +348,11 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_t3 = cv.take<double>(D);
   c->d_V = cv.take<double>((size_t)(c->restart + 1) * D);
   const bool two_level = c->pdelta >= 0.0;
-  // flexible directions: two-level preconditioner, or the FP32 sweeps of precision 1
-  c->d_Z = (two_level || c->precision == 1) ? cv.take<double>((size_t)c->restart * D) : nullptr;
-  c->d_Vin = two_level ? cv.take<double>((size_t)(c->inner_iters + 1) * D) : nullptr;
+  // flexible directions: two-level or Krylov preconditioner, or the FP32 sweeps of precision 1
+  c->d_Z = (two_level || c->pkrylov > 0 || c->precision == 1) ? cv.take<double>((size_t)c->restart * D) : nullptr;
+  c->d_Vin = (two_level || c->pkrylov > 0)
+                 ? cv.take<double>((size_t)(std::max(c->inner_iters, c->pkrylov) + 1) * D)
+                 : nullptr;
   c->d_t4 = cv.take<double>(D);
   c->d_t5 = cv.take<double>(D);
   c->d_rr = c->precision == 2 ? cv.take<double>(D) : nullptr;  // residual and correction of the refinement
@@ -1071,6 +1074,35 @@ int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b
 int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
   VecOp opL = [&](const double* in, double* out) { if (transpose) op_LT(c, in, out); else op_L(c, in, out); };
   VecOp jac = [&](const double* in, double* out) { precond(c, transpose, in, out); };
+  if (c->pkrylov > 0 && c->pdelta < 0.0) {
+    // Krylov preconditioner: pkrylov GMRES steps on L_AB (each preconditioned by the
+    // Jacobi sweeps, FP32 on the mixed path) in place of the sweeps alone; the outer
+    // method is flexible GMRES
+    VecOp opAB = [&](const double* in, double* out) {
+      if (!transpose) {
+        apply_LX(c, in, 1.0, in, -1.0, nullptr, nullptr, nullptr, 0.0, out);
+      } else {
+        syn2(c, in, 0, c->d_zr, c->d_ze);
+        apply_LTZ(c, in, 1.0, c->d_zr, c->d_ze, -1.0, nullptr, 0, out);
+      }
+    };
+    const bool fp32 = c->precision == 1 && c->use_caps;
+    VecOp jacp = [&](const double* in, double* out) {
+      const int keep = c->cur_prec;
+      if (fp32) c->cur_prec = 1;
+      precond(c, transpose, in, out);
+      c->cur_prec = keep;
+    };
+    VecOp inner = [&](const double* in, double* out) {
+      int it = 0;
+      double rr = 0;
+      (void)gmres_core(c, opAB, jacp, in, out, 1e-30, c->pkrylov, c->pkrylov, 1, true, c->d_Vin, nullptr, c->d_t4,
+                       c->d_t1, c->d_t5, &it, &rr);
+      c->inner_total += it;
+    };
+    return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
+                      c->d_t1, c->d_t2, iters, relres);
+  }
   if (c->precision == 1 && c->use_caps && c->pdelta < 0.0) {
     // FP32 Jacobi sweeps as the preconditioner of flexible GMRES on the FP64 operator:
     // the sweeps are linear only up to single-precision rounding, so the
@@ -1686,6 +1718,10 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 1 && v <= 4096)) return DDLPB_EINVAL;
     c->leaf = (int)v;
+  } else if (k == "precond_krylov") {
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v >= 0 && v <= 64)) return DDLPB_EINVAL;
+    c->pkrylov = (int)v;
   } else if (k == "apply_fp32") {
     c->apply_fp32 = v != 0;
   } else if (k == "m2l_waves") {
