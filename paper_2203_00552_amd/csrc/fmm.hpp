@@ -32,7 +32,7 @@ struct FmmDev {
   const double* J;       // packed J_l blocks
   const int* Joff;
   const double* jval;    // sparse rows of J and J^T (values)
-  const int* jrow;       // [2][L][2]: offset, first column | count << 8 | step << 16
+  const int* jrow;       // [2][L][2]: offset, first column | count << 12 | step << 20
   int njval;
   const double* center;  // [nn][3]
   const double* radius;  // [nn]
@@ -47,7 +47,7 @@ struct TransScratch {
   double bes[2 * kPmaxFmm + 4];
   double pw1[2 * kPmaxFmm + 4], pw2[2 * kPmaxFmm + 4];
   double radS[kPmaxFmm + 2], radT[kPmaxFmm + 2];
-  double ang[4];
+  double cph[kPmaxFmm + 1], sph[kPmaxFmm + 1], cth[kPmaxFmm + 1], sth[kPmaxFmm + 1];
 };
 
 // Synchronisation of the lanes cooperating on one translation: the whole block, or
@@ -65,42 +65,55 @@ __device__ __forceinline__ void tsync() {
 template <bool WAVE> __device__ __forceinline__ int tlane() { return WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
 template <bool WAVE> __device__ __forceinline__ int tstride() { return WAVE ? 64 : (int)blockDim.x; }
 
-template <bool WAVE>
-__device__ __forceinline__ void zrot_inplace(double* c, int pdeg, double alpha) {
-  // c'_m = c_m cos(m a) - c_-m sin(m a), c'_-m = c_m sin(m a) + c_-m cos(m a)
-  const int npairs = pdeg * (pdeg + 1) / 2;  // (l, m>0) pairs
-  for (int t = tlane<WAVE>(); t < npairs; t += tstride<WAVE>()) {
-    int l = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5) + 1;
-    while (l * (l - 1) / 2 > t) --l;
-    while ((l + 1) * l / 2 <= t) ++l;
-    const int m = t - l * (l - 1) / 2 + 1;
-    double s, co;
-    sincos(m * alpha, &s, &co);
-    const double a = c[lmi(l, m)], b = c[lmi(l, -m)];
-    c[lmi(l, m)] = a * co - b * s;
-    c[lmi(l, -m)] = a * s + b * co;
+__device__ __forceinline__ double ipow_d(double b, int e) {
+  double r = 1.0;
+  while (e) {
+    if (e & 1) r *= b;
+    b *= b;
+    e >>= 1;
   }
+  return r;
+}
+__device__ __forceinline__ void cpow_d(double c, double s, int e, double& rc, double& rs) {
+  double xc = 1.0, xs = 0.0;
+  while (e) {
+    if (e & 1) { const double t = xc * c - xs * s; xs = xc * s + xs * c; xc = t; }
+    const double t = c * c - s * s;
+    s = 2.0 * c * s;
+    c = t;
+    e >>= 1;
+  }
+  rc = xc;
+  rs = xs;
 }
 
-// out = J in (trans = 0) or J^T in (trans = 1), block-diagonal in l
-template <bool WAVE>
-__device__ __forceinline__ void japply(const FmmDev& f, const double* in, double* out, int pdeg, int trans) {
-  const int n = (pdeg + 1) * (pdeg + 1);
-  for (int t = tlane<WAVE>(); t < n; t += tstride<WAVE>()) {
-    const int l = (int)sqrt((double)t + 0.5);
-    const int mo = t - l * l - l;
-    const int w = 2 * l + 1;
-    const double* Jl = f.J + f.Joff[l];
+// J (mat 0) or J^T (mat 1) applied to src, written to dst (degree p)
+__device__ __forceinline__ void japply_sparse(const double* __restrict__ jv, const int* __restrict__ jr, int mat, int P,
+                                              const double* src, double* dst, int lane) {
+  for (int t = lane; t < P; t += 64) {
+    const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
+    const int cnt = (d >> 12) & 255, st = d >> 20;
+    const double* x = src + (d & 4095);
+    const double* v = jv + off;
     double s = 0.0;
-    for (int mi = -l; mi <= l; ++mi) {
-      const double jv = trans ? Jl[(mi + l) * w + (mo + l)] : Jl[(mo + l) * w + (mi + l)];
-      s += jv * in[lmi(l, mi)];
-    }
-    out[t] = s;
+    for (int k = 0; k < cnt; ++k) s += v[k] * x[st * k];
+    dst[t] = s;
   }
 }
-
-// sigma_n(z2) = i_n(z)/z^n for n = 0..nmax (series at the top, downward recurrence); lane 0 only
+// J or J^T on the degrees of a vector with Pdeg = (pdeg+1)^2 entries (row table of P entries)
+__device__ __forceinline__ void japply_sparse_deg(const double* __restrict__ jv, const int* __restrict__ jr, int mat,
+                                                  int P, int Pdeg, const double* src, double* dst, int lane) {
+  for (int t = lane; t < Pdeg; t += 64) {
+    const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
+    const int cnt = (d >> 12) & 255, st = d >> 20;
+    const double* x = src + (d & 4095);
+    const double* v = jv + off;
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += v[k] * x[st * k];
+    dst[t] = s;
+  }
+}
+// sigma_n(z2) = i_n(z)/z^n for n = 0..nmax (series at the top, downward recurrence)
 __device__ __forceinline__ void sigma_all(double z2, int nmax, double* sg) {
   double top[2];
   for (int q = 0; q < 2; ++q) {
@@ -123,7 +136,7 @@ __device__ __forceinline__ void sigma_all(double z2, int nmax, double* sg) {
     sg[l - 1] = s;
   }
 }
-// k_n(z) for n = 0..nmax (upward recurrence); lane 0 only
+// k_n(z) for n = 0..nmax (upward recurrence)
 __device__ __forceinline__ void kbes_all(double z, int nmax, double* k) {
   const double e = exp(-z);
   k[0] = 1.5707963267948966 * e / z;
@@ -131,63 +144,110 @@ __device__ __forceinline__ void kbes_all(double z, int nmax, double* k) {
   for (int l = 1; l < nmax; ++l) k[l + 1] = k[l - 1] + (2.0 * l + 1.0) / z * k[l];
 }
 
+// rotation of the pairs (l, +-m) about z by the angle with cos(m a) = co[m] (sign sg
+// (-1)^m when alt), sin(m a) = ss sg si[m]; 64 lanes
+__device__ __forceinline__ void zrot_table(double* c, int pdeg, const double* co_t, const double* si_t, bool alt,
+                                           double ss, int lane) {
+  const int npairs = pdeg * (pdeg + 1) / 2;  // (l, m>0) pairs
+  for (int t = lane; t < npairs; t += 64) {
+    int l = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f) + 1;
+    while (l * (l - 1) / 2 > t) --l;
+    while ((l + 1) * l / 2 <= t) ++l;
+    const int m = t - l * (l - 1) / 2 + 1;
+    const double sg = (alt && (m & 1)) ? -1.0 : 1.0;
+    const double co = sg * co_t[m], si = ss * sg * si_t[m];
+    const double a = c[lmi(l, m)], b = c[lmi(l, -m)];
+    c[lmi(l, m)] = a * co - b * si;
+    c[lmi(l, -m)] = a * si + b * co;
+  }
+}
+
 // Translation (kind 0 M2M, 1 M2L, 2 L2L) from node S to node T of the expansion in
 // sc.b0 (degree ps; degree pt when transposed); the result is added to acc
-// (degree pt; ps when transposed).  All lanes of the block must call it.
+// (degree pt; ps when transposed).  One 64-lane block (WAVE: one wavefront of a
+// larger block) calls it with all lanes.  The per-translation tables (Bessel
+// values, powers, node scales, cos/sin of m*phi and m*theta as powers of the unit
+// complex numbers of the centre offset) are computed one entry per lane.
 template <bool WAVE>
 __device__ void translate(const FmmDev& f, const double* __restrict__ Atab, int kind, int S, int T, int ps, int pt,
                           int transposed, TransScratch& sc, double* acc) {
-  if (tlane<WAVE>() == 0) {
-    double d[3], rho2 = 0.0;
-    for (int a = 0; a < 3; ++a) { d[a] = f.center[3 * T + a] - f.center[3 * S + a]; rho2 += d[a] * d[a]; }
-    double rho = sqrt(rho2);
-    double th = 0.0, ph = 0.0;
-    if (rho > 1e-12) {
-      th = acos(fmin(1.0, fmax(-1.0, d[2] / rho)));
-      ph = atan2(d[1], d[0]);
-    } else {
-      rho = 1e-12;
-    }
-    sc.ang[0] = th; sc.ang[1] = ph; sc.ang[2] = rho;
-    const double RS = f.radius[S], RT = f.radius[T];
-    const int nmax = ps + pt;
-    if (f.kernel == 0) {
-      const double z = f.kappa * rho;
+  const int lane = tlane<WAVE>();
+  const int P1 = f.p + 1;
+  const int nmax = ps + pt;
+  double d0 = f.center[3 * T] - f.center[3 * S], d1 = f.center[3 * T + 1] - f.center[3 * S + 1],
+         d2 = f.center[3 * T + 2] - f.center[3 * S + 2];
+  const double rxy = sqrt(d0 * d0 + d1 * d1);
+  double rho = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  double ct = 1.0, st = 0.0, cp = 1.0, sp = 0.0;
+  if (rho > 1e-12) {
+    ct = d2 / rho;
+    st = rxy / rho;
+    if (rxy > 0.0) { cp = d0 / rxy; sp = d1 / rxy; }
+  } else {
+    rho = 1e-12;
+  }
+  if (lane <= f.p) {
+    cpow_d(cp, sp, lane, sc.cph[lane], sc.sph[lane]);
+    cpow_d(ct, st, lane, sc.cth[lane], sc.sth[lane]);
+  }
+  const double RS = f.radius[S], RT = f.radius[T];
+  if (f.kernel == 0) {
+    const double z = f.kappa * rho;
+    if (lane <= nmax) {
+      const int n = lane;
       if (kind == 1) {
-        kbes_all(z, nmax, sc.bes);
-        double iz = 1.0;  // (-z)^-k
-        for (int k = 0; k <= nmax; ++k) { sc.pw1[k] = iz; iz *= -1.0 / z; }
+        // k_n(z) by the upward recurrence k_{j+1} = k_{j-1} + (2j+1)/z k_j
+        const double iz = 1.0 / z;
+        double km = 1.5707963267948966 * exp(-z) * iz, kc = km * (1.0 + iz);
+        for (int j = 1; j < n; ++j) {
+          const double kn = km + (2.0 * j + 1.0) * iz * kc;
+          km = kc;
+          kc = kn;
+        }
+        sc.bes[n] = n == 0 ? km : kc;
+        sc.pw1[n] = ipow_d(-iz, n);  // (-z)^-n
       } else {
-        sigma_all(z * z, nmax, sc.bes);
-        double zp = 1.0;
-        for (int k = 0; k <= nmax; ++k) { sc.pw1[k] = zp; zp *= z; }
+        // sigma_n(z^2) = i_n(z)/z^n = sum_k (z^2/2)^k / (k! (2n+2k+1)!!)
+        const double z2 = z * z;
+        double df = 1.0;
+        for (int k = 3; k <= 2 * n + 1; k += 2) df *= k;
+        double term = 1.0 / df, sum = term;
+        for (int k = 0; k < 400; ++k) {
+          const double ck = (n <= kLmaxDev + 1 && k < kSigTerms) ? c_sinv[n * kSigTerms + k]
+                                                                 : 0.5 / ((k + 1.0) * (2.0 * n + 2.0 * k + 3.0));
+          term *= z2 * ck;
+          sum += term;
+          if (term < 1e-18 * sum) break;
+        }
+        sc.bes[n] = sum;
+        sc.pw1[n] = ipow_d(z, n);
       }
-      for (int l = 0; l <= ps; ++l) sc.radS[l] = (kind == 2) ? 1.0 / f.iR[S * (f.p + 1) + l] : 1.0 / f.kR[S * (f.p + 1) + l];
-      for (int l = 0; l <= pt; ++l) sc.radT[l] = (kind == 0) ? f.kR[T * (f.p + 1) + l] : f.iR[T * (f.p + 1) + l];
-    } else {
-      // powers of the ratios of the Laplace translations
-      double a1, a2;
-      if (kind == 0) { a1 = RS / RT; a2 = rho / RT; }        // (RS/RT)^(l+1) (rho/RT)^(l'-l)
-      else if (kind == 1) { a1 = RT / rho; a2 = RS / rho; }  // (RT/rho)^l' (RS/rho)^(l+1)
-      else { a1 = RT / RS; a2 = rho / RS; }                  // (RT/RS)^l' (rho/RS)^(l-l')
-      double v1 = 1.0, v2 = 1.0;
-      for (int k = 0; k <= nmax + 1; ++k) { sc.pw1[k] = v1; sc.pw2[k] = v2; v1 *= a1; v2 *= a2; }
     }
+    if (lane <= ps) sc.radS[lane] = (kind == 2) ? 1.0 / f.iR[S * P1 + lane] : f.kRi[S * P1 + lane];
+    if (lane <= pt) sc.radT[lane] = (kind == 0) ? f.kR[T * P1 + lane] : f.iR[T * P1 + lane];
+  } else if (lane <= nmax + 1) {
+    // powers of the ratios of the Laplace translations
+    double a1, a2;
+    if (kind == 0) { a1 = RS / RT; a2 = rho / RT; }        // (RS/RT)^(l+1) (rho/RT)^(l'-l)
+    else if (kind == 1) { a1 = RT / rho; a2 = RS / rho; }  // (RT/rho)^l' (RS/rho)^(l+1)
+    else { a1 = RT / RS; a2 = rho / RS; }                  // (RT/RS)^l' (rho/RS)^(l-l')
+    sc.pw1[lane] = ipow_d(a1, lane);
+    sc.pw2[lane] = ipow_d(a2, lane);
   }
   tsync<WAVE>();
-  const double th = sc.ang[0], ph = sc.ang[1];
   const int pin = transposed ? pt : ps, pout = transposed ? ps : pt;
-  // rotate the input to the frame where the target sits on the -z axis
-  zrot_inplace<WAVE>(sc.b0, pin, -ph);
+  const int Pin = (pin + 1) * (pin + 1), Pout = (pout + 1) * (pout + 1);
+  // rotate the input to the frame where the target sits on the -z axis:
+  // z-rotation by -phi, J, z-rotation by pi - theta, J^T
+  zrot_table(sc.b0, pin, sc.cph, sc.sph, false, -1.0, lane);
   tsync<WAVE>();
-  japply<WAVE>(f, sc.b0, sc.b1, pin, 0);
+  japply_sparse_deg(f.jval, f.jrow, 0, P1 * P1, Pin, sc.b0, sc.b1, lane);
   tsync<WAVE>();
-  zrot_inplace<WAVE>(sc.b1, pin, 3.141592653589793 - th);
+  zrot_table(sc.b1, pin, sc.cth, sc.sth, true, -1.0, lane);
   tsync<WAVE>();
-  japply<WAVE>(f, sc.b1, sc.b0, pin, 1);
+  japply_sparse_deg(f.jval, f.jrow, 1, P1 * P1, Pin, sc.b1, sc.b0, lane);
   tsync<WAVE>();
   // translation along z
-  const int P1 = f.p + 1;
   const int nout = (pout + 1) * (pout + 1);
   for (int t = tlane<WAVE>(); t < nout; t += tstride<WAVE>()) {
     const int lo = (int)sqrt((double)t + 0.5);
@@ -220,14 +280,14 @@ __device__ void translate(const FmmDev& f, const double* __restrict__ Atab, int 
     sc.b1[t] = s;
   }
   tsync<WAVE>();
-  // rotate back
-  japply<WAVE>(f, sc.b1, sc.b0, pout, 0);
+  // rotate back: J, z-rotation by theta - pi, J^T, z-rotation by phi
+  japply_sparse_deg(f.jval, f.jrow, 0, P1 * P1, Pout, sc.b1, sc.b0, lane);
   tsync<WAVE>();
-  zrot_inplace<WAVE>(sc.b0, pout, th - 3.141592653589793);
+  zrot_table(sc.b0, pout, sc.cth, sc.sth, true, 1.0, lane);
   tsync<WAVE>();
-  japply<WAVE>(f, sc.b0, sc.b1, pout, 1);
+  japply_sparse_deg(f.jval, f.jrow, 1, P1 * P1, Pout, sc.b0, sc.b1, lane);
   tsync<WAVE>();
-  zrot_inplace<WAVE>(sc.b1, pout, ph);
+  zrot_table(sc.b1, pout, sc.cph, sc.sph, false, 1.0, lane);
   tsync<WAVE>();
   for (int t = tlane<WAVE>(); t < nout; t += tstride<WAVE>()) acc[t] += sc.b1[t];
   tsync<WAVE>();
@@ -337,43 +397,8 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __r
 //   * wavefronts take target nodes from a counter in the order given by `order`
 //     (longest lists first).
 // LDS: the tables (shared by the block) followed by one scratch area per wavefront.
-__device__ __forceinline__ double ipow_d(double b, int e) {
-  double r = 1.0;
-  while (e) {
-    if (e & 1) r *= b;
-    b *= b;
-    e >>= 1;
-  }
-  return r;
-}
-__device__ __forceinline__ void cpow_d(double c, double s, int e, double& rc, double& rs) {
-  double xc = 1.0, xs = 0.0;
-  while (e) {
-    if (e & 1) { const double t = xc * c - xs * s; xs = xc * s + xs * c; xc = t; }
-    const double t = c * c - s * s;
-    s = 2.0 * c * s;
-    c = t;
-    e >>= 1;
-  }
-  rc = xc;
-  rs = xs;
-}
-
 __host__ __device__ constexpr int m2l_fast_wave_doubles(int p) { return 2 * (p + 1) * (p + 1) + 8 * (p + 1); }
 
-// J (mat 0) or J^T (mat 1) applied to src, written to dst (degree p)
-__device__ __forceinline__ void japply_sparse(const double* __restrict__ jv, const int* __restrict__ jr, int mat, int P,
-                                              const double* src, double* dst, int lane) {
-  for (int t = lane; t < P; t += 64) {
-    const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
-    const int cnt = (d >> 12) & 255, st = d >> 20;
-    const double* x = src + (d & 4095);
-    const double* v = jv + off;
-    double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += v[k] * x[st * k];
-    dst[t] = s;
-  }
-}
 // order m of the lane's item i, packed 6 bits per item (offset 32)
 __device__ __forceinline__ int item_m(int mpack, int i) { return ((mpack >> (6 * i)) & 63) - 32; }
 __device__ __forceinline__ int item_l(int lpack, int i) { return (lpack >> (6 * i)) & 63; }
