@@ -163,7 +163,9 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field kernels of the mixed
  *                    path (diagnostic: operator error of the mixed path)
  *   "m2l_waves"      wavefronts per block of the multipole-to-local kernel
- *                    (0 = chosen from the occupancy calculator; 1, 2, 4, 8, 16)
+ *                    (0 = chosen from the occupancy calculator; 1, 2, 4, 8, 16;
+ *                    -1 = the one-node-per-block kernel built on the generic
+ *                    translation, a reference for the fast kernel)
  *   "kernel_timing"  1: record the device time of every kernel launch with HIP
  *                    events on the context's stream (see ddlpb_kernel_times)
  * Errors: EINVAL (unknown key or value out of range), ESTATE.
@@ -172,8 +174,10 @@ int ddlpb_set_option(ddlpb_ctx* ctx, const char* key, double value);
 
 /*
  * ddlpb_update_centers -- new conformation of the same molecule (same radii,
- * charges and parameters); [M][3] host.  X and X_adj are kept as initial
- * guesses of the next solves.  Errors: EINVAL, EGEOM.
+ * charges and parameters); [M][3] host.  Neighbour lists, caps and (with the
+ * FMM) the tree and its interaction lists are rebuilt for the new centres; X
+ * and X_adj are kept as initial guesses of the next solves.  Errors: EINVAL,
+ * EGEOM, ENOMEM (a bound workspace too small for the new lists).
  */
 int ddlpb_update_centers(ddlpb_ctx* ctx, const double* centers);
 

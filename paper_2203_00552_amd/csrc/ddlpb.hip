@@ -87,7 +87,7 @@ struct ddlpb_ctx {
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
   double theta = 0.6;
-  int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic)
+  int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic, -1: block kernel)
   int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
   struct M2LCfg { bool valid = false, alds = false; int nw = 0, per_cu = 0; size_t bytes = 0; } m2l_cfg[2];
   // ---- host analysis
@@ -751,7 +751,7 @@ void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes, in
   alds = false;
   bytes = 0;
   blocks_per_cu = 0;
-  if (NI > 5) return;
+  if (NI > 5 || c->m2l_waves < 0) return;
   int best = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool a = pass == 0;
@@ -1725,7 +1725,7 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "apply_fp32") {
     c->apply_fp32 = v != 0;
   } else if (k == "m2l_waves") {
-    if (!(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
+    if (!(v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
     c->m2l_cfg[0].valid = c->m2l_cfg[1].valid = false;
   } else if (k == "theta") {
@@ -1754,8 +1754,15 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
     int rc = build_neighbours(c);
     if (rc) { c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; return rc; }
     build_pairs(c, c->pdelta, c->pptr, c->pidx);
+    if (c->fmm_order > 0) {
+      // the leaves sit at the sphere centres: the tree and its lists follow the atoms
+      fmm::build_tree(c->M, c->x.data(), c->r.data(), c->tree);
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+    }
     if (c->dev_ready) {
-      const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap || c->cap_est > c->cap_cap;
+      const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap || c->cap_est > c->cap_cap ||
+                            (c->fmm_order > 0 && (c->tree.m2l_src.size() > c->m2l_cap ||
+                                                  c->tree.near_idx.size() > c->near_cap));
       if (relayout) {
         // list capacities exceeded: the workspace layout changes; keep X and X_adj
         std::vector<double> X(2L * c->M * c->L), Xa(2L * c->M * c->L);
@@ -1765,6 +1772,10 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
         c->nnz_cap = c->nidx.size() + c->nidx.size() / 4 + 64;
         c->pnz_cap = c->pidx.size() + c->pidx.size() / 4 + 64;
         c->cap_cap = c->cap_est + c->cap_est / 4 + 64;
+        if (c->fmm_order > 0) {
+          c->m2l_cap = c->tree.m2l_src.size() + c->tree.m2l_src.size() / 4 + 64;
+          c->near_cap = c->tree.near_idx.size() + c->tree.near_idx.size() / 4 + 64;
+        }
         size_t need = workspace_size(c);
         if (c->ws_bound && need > c->ws_bytes) return DDLPB_ENOMEM;
         if (c->ws_owned && need > c->ws_bytes) {

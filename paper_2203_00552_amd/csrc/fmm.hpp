@@ -87,19 +87,6 @@ __device__ __forceinline__ void cpow_d(double c, double s, int e, double& rc, do
   rs = xs;
 }
 
-// J (mat 0) or J^T (mat 1) applied to src, written to dst (degree p)
-__device__ __forceinline__ void japply_sparse(const double* __restrict__ jv, const int* __restrict__ jr, int mat, int P,
-                                              const double* src, double* dst, int lane) {
-  for (int t = lane; t < P; t += 64) {
-    const int off = jr[2 * (mat * P + t)], d = jr[2 * (mat * P + t) + 1];
-    const int cnt = (d >> 12) & 255, st = d >> 20;
-    const double* x = src + (d & 4095);
-    const double* v = jv + off;
-    double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += v[k] * x[st * k];
-    dst[t] = s;
-  }
-}
 // J or J^T on the degrees of a vector with Pdeg = (pdeg+1)^2 entries (row table of P entries)
 __device__ __forceinline__ void japply_sparse_deg(const double* __restrict__ jv, const int* __restrict__ jr, int mat,
                                                   int P, int Pdeg, const double* src, double* dst, int lane) {
@@ -560,11 +547,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
       }
       if (q + 1 < q1) fetch(lidx[q + 1]);
       tsync<true>();
-      japply_sparse(jv, jr, 0, P, b0, b1, lane);
+      japply_sparse_deg(jv, jr, 0, P, P, b0, b1, lane);
       tsync<true>();
       zrot_alt<NI>(b1, P, cth, sth, -1.0, lane, mpack);  // pi - theta
       tsync<true>();
-      japply_sparse(jv, jr, 1, P, b1, b0, lane);
+      japply_sparse_deg(jv, jr, 1, P, P, b1, b0, lane);
       tsync<true>();
       // translation along z
       for (int s = lane; s < zt.nslot; s += 64) {
@@ -591,11 +578,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         if (am) b1[lo * lo + lo - am] = sm;
       }
       tsync<true>();
-      japply_sparse(jv, jr, 0, P, b1, b0, lane);
+      japply_sparse_deg(jv, jr, 0, P, P, b1, b0, lane);
       tsync<true>();
       zrot_alt<NI>(b0, P, cth, sth, 1.0, lane, mpack);  // theta - pi
       tsync<true>();
-      japply_sparse(jv, jr, 1, P, b0, b1, lane);
+      japply_sparse_deg(jv, jr, 1, P, P, b0, b1, lane);
       tsync<true>();
       // rotation by phi, scaled by degree, accumulated in registers
 #pragma unroll

@@ -63,6 +63,42 @@ def test_m2l_block_layouts_agree(cluster):
         assert _rel(a, out[0][0]) < 1e-13 and _rel(b, out[0][1]) < 1e-13
 
 
+def test_m2l_generic_kernel_agrees(cluster):
+    """The one-node-per-block M2L kernel built on the generic translation (the one
+    the M2M and L2L passes use) and the wavefront M2L kernel give the same operator."""
+    x, r, q = cluster
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(2, len(r), 49))
+    out = []
+    for w in (0, -1):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=10, options={"m2l_waves": w})
+        out.append((f.apply(X), f.apply(X, transpose=True)))
+        f.close()
+    assert _rel(out[1][0], out[0][0]) < 1e-12 and _rel(out[1][1], out[0][1]) < 1e-12
+
+
+def test_update_centers_rebuilds_tree():
+    """A context moved to new centres (ddlpb_update_centers) with the FMM gives the
+    energy and forces of a context created at those centres: the tree and its
+    interaction lists follow the atoms."""
+    x, r, q = inputs.lattice_cluster(1500, seed=10)
+    x2 = x + 0.3 * np.random.default_rng(1).normal(size=x.shape)
+    a = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=10)
+    a.solve(1e-10)
+    a.update_centers(x2)
+    Ea = a.solve(1e-10)
+    a.adjoint(1e-10)
+    Fa = a.forces()
+    b = Context(x2, r, q, lmax=6, n_lebedev=302, fmm_order=10)
+    Eb = b.solve(1e-10)
+    b.adjoint(1e-10)
+    Fb = b.forces()
+    assert abs(Ea / Eb - 1) < 1e-9
+    assert _rel(Fa, Fb) < 1e-7
+    a.close()
+    b.close()
+
+
 def test_fmm_error_decreases_with_order(cluster):
     """At a fixed acceptance parameter the far-field error falls with the expansion
     order (the local expansions are evaluated on the sphere grids to full degree p)."""
