@@ -135,11 +135,12 @@ struct ddlpb_ctx {
          *d_qsrc = nullptr, *d_tmp4 = nullptr;
   double* d_fjval = nullptr;
   int* d_fjrow = nullptr;
+  double* d_fjpad = nullptr;
   double* d_fZ[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [kernel][direction]
   int* d_fZslot[2] = {nullptr, nullptr};
-  int *d_fm2lord = nullptr, *d_fm2ltord = nullptr, *d_fctr = nullptr;
+  int *d_fm2lord = nullptr, *d_fctr = nullptr;
   int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
-      *d_fm2ls = nullptr, *d_fm2ltp = nullptr, *d_fm2ltt = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
+      *d_fm2ls = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
       *d_sleaf = nullptr;
   double near_pts_fmm = 0.0;  // (active point, near source sphere) pairs of the FMM near list
   // ---- per-kernel device timing (option "kernel_timing")
@@ -396,8 +397,6 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
     c->d_sleaf = cv.take<int>(M);
     c->d_fm2lp = cv.take<int>(nn + 1);
     c->d_fm2ls = cv.take<int>(std::max<size_t>(c->m2l_cap, 1));
-    c->d_fm2ltp = cv.take<int>(nn + 1);
-    c->d_fm2ltt = cv.take<int>(std::max<size_t>(c->m2l_cap, 1));
     c->d_fnp = cv.take<int>(M + 1);
     c->d_fni = cv.take<int>(std::max<size_t>(c->near_cap, 1));
     c->d_fA = cv.take<double>(std::max<size_t>(c->tables.Ap.size(), 1));
@@ -407,12 +406,12 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
     c->d_fJoff = cv.take<int>(p1 + 1);
     c->d_fjval = cv.take<double>(std::max<size_t>(c->tables.Jval.size(), 1));
     c->d_fjrow = cv.take<int>(std::max<size_t>(c->tables.Jrow.size(), 1));
+    c->d_fjpad = cv.take<double>(std::max<size_t>(c->tables.Jpad.size(), 1));
     for (int k = 0; k < 2; ++k) {
       for (int d = 0; d < 2; ++d) c->d_fZ[k][d] = cv.take<double>(std::max<size_t>(c->tables.Z[k][d].size(), 1));
       c->d_fZslot[k] = cv.take<int>(std::max<size_t>(c->tables.Zslot[k].size(), 1));
     }
     c->d_fm2lord = cv.take<int>(nn);
-    c->d_fm2ltord = cv.take<int>(nn);
     c->d_fctr = cv.take<int>(64);
     c->d_Mn = cv.take<double>(nn * P);
     c->d_Ln = cv.take<double>(nn * P);
@@ -718,18 +717,22 @@ inline double flops_m2l_fast(int kernel, int p, size_t njval) {
   const double P = (p + 1.0) * (p + 1.0);
   return 2.0 * 2.0 * (double)njval + 4.0 * 6.0 * p * (p + 1) / 2.0 + 2.0 * P + oz;
 }
-template <int NI>
+template <int NI, bool YUK>
 const void* m2l_fast_fn(bool alds) {
-  return alds ? reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, true>)
-              : reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, false>);
+  return alds ? reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, true, YUK>)
+              : reinterpret_cast<const void*>(&k_fmm_m2l_fast<NI, false, YUK>);
 }
-const void* m2l_fast_fn(int NI, bool alds) {
+template <int NI>
+const void* m2l_fast_fn(int kernel, bool alds) {
+  return kernel == 0 ? m2l_fast_fn<NI, true>(alds) : m2l_fast_fn<NI, false>(alds);
+}
+const void* m2l_fast_fn(int NI, int kernel, bool alds) {
   switch (NI) {
-    case 1: return m2l_fast_fn<1>(alds);
-    case 2: return m2l_fast_fn<2>(alds);
-    case 3: return m2l_fast_fn<3>(alds);
-    case 4: return m2l_fast_fn<4>(alds);
-    default: return m2l_fast_fn<5>(alds);
+    case 1: return m2l_fast_fn<1>(kernel, alds);
+    case 2: return m2l_fast_fn<2>(kernel, alds);
+    case 3: return m2l_fast_fn<3>(kernel, alds);
+    case 4: return m2l_fast_fn<4>(kernel, alds);
+    default: return m2l_fast_fn<5>(kernel, alds);
   }
 }
 // Block layout of k_fmm_m2l_fast: the most resident wavefronts per compute unit as
@@ -746,16 +749,16 @@ void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes, in
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const int p = c->fmm_order, P = (p + 1) * (p + 1), NI = (P + 63) / 64;
   const auto& tb = c->tables;
-  const int nZ = (int)tb.Z[kernel][0].size(), nj = (int)tb.Jval.size();
+  const int nZ = (int)tb.Z[kernel][0].size(), nj = (int)tb.Jpad.size();
   nw = 0;
   alds = false;
   bytes = 0;
   blocks_per_cu = 0;
-  if (NI > 5 || c->m2l_waves < 0) return;
+  if (NI > 5 || c->m2l_waves < 0 || !tb.jpad_ok) return;
   int best = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool a = pass == 0;
-    const void* fn = m2l_fast_fn(NI, a);
+    const void* fn = m2l_fast_fn(NI, kernel, a);
     for (int w : {16, 8, 4, 2, 1}) {
       if (c->m2l_waves > 0 && w != c->m2l_waves) continue;
       const size_t b = m2l_fast_lds_bytes(p, nZ, nj, tb.nslot, w, a);
@@ -775,12 +778,10 @@ void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes, in
 template <int NI>
 void launch_m2l_fast(ddlpb_ctx* c, const FmmDev& f, const M2LTab& zt, int nw, bool alds, size_t bytes, int blocks,
                      const int* lptr, const int* lidx, int transposed, const double* in, double* out) {
-  if (alds)
-    hipLaunchKernelGGL((k_fmm_m2l_fast<NI, true>), dim3(blocks), dim3(64 * nw), bytes, c->stream, f, zt,
-                       c->tree.nnodes, lptr, lidx, transposed, in, out);
-  else
-    hipLaunchKernelGGL((k_fmm_m2l_fast<NI, false>), dim3(blocks), dim3(64 * nw), bytes, c->stream, f, zt,
-                       c->tree.nnodes, lptr, lidx, transposed, in, out);
+  const void* fn = m2l_fast_fn(NI, f.kernel, alds);
+  void* args[] = {(void*)&f, (void*)&zt, (void*)&c->tree.nnodes, (void*)&lptr, (void*)&lidx, (void*)&transposed,
+                  (void*)&in, (void*)&out};
+  HIPCHK(hipLaunchKernel(fn, dim3(blocks), dim3(64 * nw), args, bytes, c->stream));
 }
 __global__ void k_zero_ints(int* p, int n) {
   for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
@@ -805,10 +806,13 @@ void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx,
     M2LTab zt;
     zt.Z = c->d_fZ[f.kernel][transposed ? 1 : 0];
     zt.slot = c->d_fZslot[f.kernel];
-    zt.order = transposed ? c->d_fm2ltord : c->d_fm2lord;
+    zt.order = c->d_fm2lord;
     zt.counter = c->d_fctr;
     zt.nZ = (int)tb.Z[f.kernel][0].size();
     zt.nslot = tb.nslot;
+    zt.jpad = c->d_fjpad;
+    zt.njpad = (int)tb.Jpad.size();
+    zt.kpack = tb.jpad_kpack;
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 1);
     switch (NI) {
       case 1: launch_m2l_fast<1>(c, f, zt, nw, alds, bytes, blocks, lptr, lidx, transposed, in, out); break;
@@ -859,7 +863,7 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
     hipLaunchKernelGGL(k_fmm_upward_T, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
                        c->d_fchild, c->d_Ln);
   }
-  launch_m2l(c, f, c->d_fm2ltp, c->d_fm2ltt, 1, c->d_Ln, c->d_Mn);
+  launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 1, c->d_Ln, c->d_Mn);  // symmetric lists: by source
   for (int lev = 1; lev < t.nlevels; ++lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
     hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
@@ -1261,6 +1265,7 @@ void upload_and_init(ddlpb_ctx* c) {
     up(c->d_fJoff, c->tables.Joff.data(), c->tables.Joff.size() * sizeof(int));
     up(c->d_fjval, c->tables.Jval.data(), c->tables.Jval.size() * sizeof(double));
     up(c->d_fjrow, c->tables.Jrow.data(), c->tables.Jrow.size() * sizeof(int));
+    up(c->d_fjpad, c->tables.Jpad.data(), c->tables.Jpad.size() * sizeof(double));
     for (int k = 0; k < 2; ++k) {
       for (int d = 0; d < 2; ++d) up(c->d_fZ[k][d], c->tables.Z[k][d].data(), c->tables.Z[k][d].size() * sizeof(double));
       up(c->d_fZslot[k], c->tables.Zslot[k].data(), c->tables.Zslot[k].size() * sizeof(int));
@@ -1300,10 +1305,7 @@ void upload_tree(ddlpb_ctx* c) {
   up(c->d_sleaf, t.sphere_leaf.data(), t.sphere_leaf.size() * sizeof(int));
   up(c->d_fm2lp, t.m2l_ptr.data(), t.m2l_ptr.size() * sizeof(int));
   up(c->d_fm2ls, t.m2l_src.data(), t.m2l_src.size() * sizeof(int));
-  up(c->d_fm2ltp, t.m2lt_ptr.data(), t.m2lt_ptr.size() * sizeof(int));
-  up(c->d_fm2ltt, t.m2lt_tgt.data(), t.m2lt_tgt.size() * sizeof(int));
   up(c->d_fm2lord, t.m2l_order.data(), t.m2l_order.size() * sizeof(int));
-  up(c->d_fm2ltord, t.m2lt_order.data(), t.m2lt_order.size() * sizeof(int));
   up(c->d_fnp, t.near_ptr.data(), t.near_ptr.size() * sizeof(int));
   up(c->d_fni, t.near_idx.data(), t.near_idx.size() * sizeof(int));
   hipLaunchKernelGGL(k_fmm_node_radial, dim3(nblk(t.nnodes, 128)), dim3(128), 0, c->stream, t.nnodes, c->fmm_order,

@@ -409,40 +409,64 @@ __device__ __forceinline__ void zrot_alt(double* b, int P, const double* c, cons
 
 // z-translation table of one M2L launch (kernel type and direction)
 struct M2LTab {
-  const double* Z;  // entries, see the host tables
-  const int* slot;  // [nslot][2]: lo << 8 | |m| (or -1), offset
-  const int* order; // target node order (longest lists first)
-  int* counter;     // work counter, zero at launch
-  int nZ, nslot;
+  const double* Z;     // entries, see the host tables
+  const int* slot;     // [nslot][2]: lo << 8 | |m| (or -1), offset
+  const int* order;    // target node order (longest lists first)
+  int* counter;        // work counter, zero at launch
+  const double* jpad;  // rows of J and J^T padded per group of 64, [mat][g][k][lane]
+  int nZ, nslot, njpad;
+  int kpack;           // padded row length of group g in bits 4g..4g+3 (even)
 };
 
-template <int NI, bool ALDS>
+// J or J^T (one matrix of the padded table, already offset by the lane) applied to
+// src: lane row t = lane + 64 i sums K_i products with a step of 2 along src; the
+// padding has zero values (its src reads stay inside the wavefront's scratch, which
+// holds finite values only).  The trip counts are uniform over the wavefront.
+template <int NI>
+__device__ __forceinline__ void japply_pad(const double* v, const int (&xb)[NI], int shift, int kpack,
+                                           const double* src, double* dst, int lane, int P) {
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int K = (kpack >> (4 * i)) & 15;
+    const double* x = src + ((xb[i] >> shift) & 0xffff);
+    double s = 0.0;
+    for (int k = 0; k < K; k += 2) {
+      s = fma(v[0], x[0], s);
+      s = fma(v[64], x[2], s);
+      v += 128;
+      x += 4;
+    }
+    if (lane + 64 * i < P) dst[lane + 64 * i] = s;
+  }
+}
+
+template <int NI, bool ALDS, bool YUK>
 __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int nn, const int* __restrict__ lptr,
                                                        const int* __restrict__ lidx, int transposed,
                                                        const double* __restrict__ Ein, double* __restrict__ Eout) {
   extern __shared__ double smem[];
   const int p = f.p, P1 = p + 1, P = P1 * P1;
   const int nw = blockDim.x >> 6;
-  const bool yuk = f.kernel == 0;
+  const int wd = m2l_fast_wave_doubles(p);
   // block-shared tables
   double* jv = smem;
-  double* zl = jv + f.njval;
+  double* zl = jv + zt.njpad;
   double* wsb = zl + (ALDS ? zt.nZ : 0);
-  int* jr = (int*)(wsb + nw * m2l_fast_wave_doubles(p));
-  int* zs = jr + 4 * P;
-  for (int t = threadIdx.x; t < f.njval; t += blockDim.x) jv[t] = f.jval[t];
-  for (int t = threadIdx.x; t < 4 * P; t += blockDim.x) jr[t] = f.jrow[t];
+  int* zs = (int*)(wsb + nw * wd);
+  for (int t = threadIdx.x; t < zt.njpad; t += blockDim.x) jv[t] = zt.jpad[t];
   for (int t = threadIdx.x; t < 2 * zt.nslot; t += blockDim.x) zs[t] = zt.slot[t];
   if constexpr (ALDS) {
     for (int t = threadIdx.x; t < zt.nZ; t += blockDim.x) zl[t] = zt.Z[t];
   }
+  // the padded J reads may run past a vector into the scratch behind it: start finite
+  for (int t = threadIdx.x; t < nw * wd; t += blockDim.x) wsb[t] = 0.0;
   __syncthreads();
   const double* Z;
   if constexpr (ALDS) Z = zl; else Z = zt.Z;
 
   // the wavefront index is uniform: keep it (and every scratch address) in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  double* b0 = wsb + w * m2l_fast_wave_doubles(p);
+  double* b0 = wsb + w * wd;
   double* b1 = b0 + P;
   double* kt = b1 + P;         // k_n(z) z^n, n = 0..2p (2p+2)
   double* sIn = kt + 2 * P1;   // degree scale of the input
@@ -451,15 +475,18 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
   double* sph = cph + P1;
   double* cth = sph + P1;
   double* sth = cth + P1;
+  const int nj = zt.njpad / 2;
 
-  // lane items t = lane + 64 i: degree and order, 6 bits each
+  // lane items t = lane + 64 i: degree and order, 6 bits each; first column of the J rows
   int mpack = 0, lpack = 0;
+  int xb[NI];  // first column of the row of J (low 16 bits) and of J^T (high 16 bits)
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int t = lane + 64 * i;
     const int l = (int)sqrtf((float)t + 0.5f);
     mpack |= ((t - l * l - l + 32) & 63) << (6 * i);
     lpack |= (l & 63) << (6 * i);
+    xb[i] = t < P ? ((f.jrow[2 * t + 1] & 4095) | ((f.jrow[2 * (P + t) + 1] & 4095) << 16)) : 0;
   }
 
   for (;;) {
@@ -475,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
     // data of the fixed node n (target, or source when transposed): i_l(kappa R) or 1/k_l(kappa R)
     const double cnx = f.center[3 * n], cny = f.center[3 * n + 1], cnz = f.center[3 * n + 2];
     double rfix = 0.0;
-    if (yuk && lane <= p) rfix = transposed ? f.kRi[n * P1 + lane] : f.iR[n * P1 + lane];
+    if (YUK && lane <= p) rfix = transposed ? f.kRi[n * P1 + lane] : f.iR[n * P1 + lane];
     // first source, fetched ahead
     double va[NI], vb[NI], vc = 0.0, vr = 0.0;
     auto fetch = [&](int o) {
@@ -488,7 +515,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
       }
       vc = lane < 3 ? f.center[3 * o + lane] : 0.0;
       vr = 0.0;
-      if (yuk && lane <= p) vr = transposed ? f.iR[o * P1 + lane] : f.kRi[o * P1 + lane];
+      if (YUK && lane <= p) vr = transposed ? f.iR[o * P1 + lane] : f.kRi[o * P1 + lane];
     };
     if (q0 < q1) fetch(lidx[q0]);
     for (int q = q0; q < q1; ++q) {
@@ -506,7 +533,7 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         cpow_d(c1, s1, lane, cph[lane], sph[lane]);
         cpow_d(dz * irho, rxy * irho, lane, cth[lane], sth[lane]);
         double u, v;  // source-degree and target-degree scales
-        if (yuk) {
+        if constexpr (YUK) {
           // k-sum against k_n(z) z^n; z^-(l+l') (-1)^l and the node scales go to the degrees
           const double zi = irho * f.kinv;
           const double zl = ipow_d(zi, lane);
@@ -521,15 +548,16 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         sIn[lane] = transposed ? v : u;
         sOut[lane] = transposed ? u : v;
       }
-      if (yuk && lane <= 2 * p) {
+      if (YUK && lane <= 2 * p) {
         // k_n(z) z^n by the upward recurrence kt_{n+1} = z^2 kt_{n-1} + (2n+1) kt_n
         const double z = f.kappa * rho, z2 = z * z;
         double km = 1.5707963267948966 * exp(-z) * irho * f.kinv;
-        double kc = km * (z + 1.0);
+        double kc = km * (z + 1.0), c = 3.0;
         for (int j = 1; j < lane; ++j) {
-          const double kn = z2 * km + (2.0 * j + 1.0) * kc;
+          const double kn = z2 * km + c * kc;
           km = kc;
           kc = kn;
+          c += 2.0;
         }
         kt[lane] = lane == 0 ? km : kc;
       }
@@ -547,11 +575,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
       }
       if (q + 1 < q1) fetch(lidx[q + 1]);
       tsync<true>();
-      japply_sparse_deg(jv, jr, 0, P, P, b0, b1, lane);
+      japply_pad<NI>(jv + lane, xb, 0, zt.kpack, b0, b1, lane, P);
       tsync<true>();
       zrot_alt<NI>(b1, P, cth, sth, -1.0, lane, mpack);  // pi - theta
       tsync<true>();
-      japply_sparse_deg(jv, jr, 1, P, P, b1, b0, lane);
+      japply_pad<NI>(jv + nj + lane, xb, 16, zt.kpack, b1, b0, lane, P);
       tsync<true>();
       // translation along z
       for (int s = lane; s < zt.nslot; s += 64) {
@@ -562,11 +590,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         double sp = 0.0, sm = 0.0;
         for (int li = am; li <= p; ++li) {
           double e;
-          if (yuk) {
+          if constexpr (YUK) {
             const int nk = min(lo, li) - am + 1;
             const double* kp = kt + lo + li - am;
             e = 0.0;
-            for (int kk = 0; kk < nk; ++kk) e += zp[kk] * kp[-kk];
+            for (int kk = 0; kk < nk; ++kk) e = fma(zp[kk], kp[-kk], e);
             zp += nk;
           } else {
             e = *zp++;
@@ -578,11 +606,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         if (am) b1[lo * lo + lo - am] = sm;
       }
       tsync<true>();
-      japply_sparse_deg(jv, jr, 0, P, P, b1, b0, lane);
+      japply_pad<NI>(jv + lane, xb, 0, zt.kpack, b1, b0, lane, P);
       tsync<true>();
       zrot_alt<NI>(b0, P, cth, sth, 1.0, lane, mpack);  // theta - pi
       tsync<true>();
-      japply_sparse_deg(jv, jr, 1, P, P, b0, b1, lane);
+      japply_pad<NI>(jv + nj + lane, xb, 16, zt.kpack, b0, b1, lane, P);
       tsync<true>();
       // rotation by phi, scaled by degree, accumulated in registers
 #pragma unroll
@@ -605,11 +633,9 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
 }
 
 // LDS bytes of k_fmm_m2l_fast for nw wavefronts per block
-inline size_t m2l_fast_lds_bytes(int p, int nZ, int njval, int nslot, int nw, bool alds) {
-  const size_t P1 = p + 1, P = P1 * P1;
-  const size_t d = (size_t)njval + (alds ? (size_t)nZ : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
-  const size_t i = 4 * P + 2 * (size_t)nslot;
-  return d * sizeof(double) + i * sizeof(int);
+inline size_t m2l_fast_lds_bytes(int p, int nZ, int njpad, int nslot, int nw, bool alds) {
+  const size_t d = (size_t)njpad + (alds ? (size_t)nZ : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
+  return d * sizeof(double) + 2 * (size_t)nslot * sizeof(int);
 }
 
 // downward pass of one level: L[n] += L2L(parent -> n) L[parent]

@@ -5,14 +5,17 @@
 // widest axis; every leaf is one sphere (so a leaf expansion is the sphere's own
 // expansion, centred at x_j with scale r_j).  Node radius R encloses every grid
 // point of the node's spheres (max |x_j - c| + r_j).
-// Lists: dual traversal with the acceptance test R_T + R_S < theta |c_T - c_S|;
+// Lists: symmetric dual traversal with the acceptance test R_T + R_S < theta |c_T - c_S|;
 // accepted pairs are multipole-to-local translations, rejected leaf pairs are
 // evaluated directly (near list, sphere pairs).
 #pragma once
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <functional>
 #include <numeric>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "host_math.hpp"
@@ -31,10 +34,11 @@ struct Tree {
   std::vector<int> sphere_leaf;   // [M], node index of the sphere's leaf
   std::vector<int> level_ptr, level_nodes;  // nodes grouped by level (CSR)
   // interaction lists
-  std::vector<int> m2l_ptr, m2l_src;  // per target node, source nodes (sorted)
-  std::vector<int> m2lt_ptr, m2lt_tgt;  // transposed: per source node, target nodes
+  // per target node, source nodes (sorted); the lists are symmetric, so the list of a
+  // node is also the list of targets it is a source for (the transposed lists)
+  std::vector<int> m2l_ptr, m2l_src;
   std::vector<int> near_ptr, near_idx;  // per target sphere, source spheres (self included)
-  std::vector<int> m2l_order, m2lt_order;  // nodes by decreasing list length (work order)
+  std::vector<int> m2l_order;  // nodes by decreasing list length (work order)
 };
 
 inline void build_tree(int M, const double* x, const double* r, Tree& t) {
@@ -97,63 +101,117 @@ inline void build_tree(int M, const double* x, const double* r, Tree& t) {
   for (int n = 0; n < t.nnodes; ++n) t.level_nodes[fillp[t.level[n]]++] = n;
 }
 
+// Runs body(i) for i in [0, n) on up to 16 host threads (dynamic chunks of `chunk`).
+template <class F>
+inline void parallel_for(long n, long chunk, F body) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<long> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const long i0 = next.fetch_add(chunk);
+      if (i0 >= n) return;
+      for (long i = i0; i < std::min(n, i0 + chunk); ++i) body(i);
+    }
+  };
+  if (nt == 1 || n <= chunk) { work(); return; }
+  std::vector<std::thread> th;
+  for (int k = 1; k < nt; ++k) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+}
+
+// CSR of the pairs (key, value) grouped by key (nkeys keys), values of a key sorted
+// increasingly; pairs come in per-task vectors.
+inline void pairs_to_csr(const std::vector<std::vector<std::pair<int, int>>>& parts, int nkeys,
+                         std::vector<int>& ptr, std::vector<int>& idx) {
+  std::vector<std::atomic<int>> cnt(nkeys + 1);
+  for (auto& c : cnt) c.store(0, std::memory_order_relaxed);
+  parallel_for((long)parts.size(), 1, [&](long k) {
+    for (const auto& pr : parts[k]) cnt[pr.first].fetch_add(1, std::memory_order_relaxed);
+  });
+  ptr.assign(nkeys + 1, 0);
+  for (int n = 0; n < nkeys; ++n) ptr[n + 1] = ptr[n] + cnt[n].load(std::memory_order_relaxed);
+  idx.assign(ptr[nkeys], 0);
+  for (int n = 0; n < nkeys; ++n) cnt[n].store(ptr[n], std::memory_order_relaxed);
+  parallel_for((long)parts.size(), 1, [&](long k) {
+    for (const auto& pr : parts[k]) idx[cnt[pr.first].fetch_add(1, std::memory_order_relaxed)] = pr.second;
+  });
+  parallel_for(nkeys, 1024, [&](long n) { std::sort(idx.begin() + ptr[n], idx.begin() + ptr[n + 1]); });
+}
+
+// Interaction lists by a symmetric dual traversal: self(A) = self(A1) + self(A2) +
+// mutual(A1, A2); mutual(A, B) is accepted as the two translations A -> B and B -> A
+// when R_A + R_B < theta |c_A - c_B|, is a near pair (both ways) when both are
+// leaves, and otherwise splits the larger node (ties by index).  The list of every
+// node is therefore also its transposed list.  The traversal is expanded
+// breadth-first into a frontier of pending tasks that host threads finish
+// depth-first; the lists are assembled by counting sorts with each list sorted, so
+// the result does not depend on the thread schedule.
 inline void build_lists(int M, const double* r, double theta, Tree& t) {
-  std::vector<std::vector<int>> m2l(t.nnodes);
-  std::vector<std::vector<int>> near(M);
   auto is_leaf = [&](int n) { return t.child[2 * n] < 0; };
-  std::function<void(int, int)> interact = [&](int T, int S) {
+  using Pairs = std::vector<std::pair<int, int>>;
+  // one task (A == B: self, else mutual): emits pairs, appends subtasks to `sub`
+  auto visit = [&](int A, int B, Pairs& om, Pairs& on, Pairs& sub) {
+    if (A == B) {
+      if (is_leaf(A)) { on.push_back({t.leaf_sphere[A], t.leaf_sphere[A]}); return; }
+      const int c1 = t.child[2 * A], c2 = t.child[2 * A + 1];
+      sub.push_back({c1, c2});
+      sub.push_back({c2, c2});
+      sub.push_back({c1, c1});
+      return;
+    }
     double d2 = 0;
-    for (int a = 0; a < 3; ++a) { double v = t.center[3 * T + a] - t.center[3 * S + a]; d2 += v * v; }
-    const double d = std::sqrt(d2);
-    if (T != S && t.radius[T] + t.radius[S] < theta * d) {
-      m2l[T].push_back(S);
+    for (int a = 0; a < 3; ++a) { double v = t.center[3 * A + a] - t.center[3 * B + a]; d2 += v * v; }
+    if (t.radius[A] + t.radius[B] < theta * std::sqrt(d2)) {
+      om.push_back({A, B});
+      om.push_back({B, A});
       return;
     }
-    const bool lt = is_leaf(T), ls = is_leaf(S);
-    if (lt && ls) {
-      near[t.leaf_sphere[T]].push_back(t.leaf_sphere[S]);
+    const bool la = is_leaf(A), lb = is_leaf(B);
+    if (la && lb) {
+      on.push_back({t.leaf_sphere[A], t.leaf_sphere[B]});
+      on.push_back({t.leaf_sphere[B], t.leaf_sphere[A]});
       return;
     }
-    if (ls || (!lt && t.radius[T] >= t.radius[S])) {
-      interact(t.child[2 * T], S);
-      interact(t.child[2 * T + 1], S);
+    const bool split_a = lb || (!la && (t.radius[A] > t.radius[B] || (t.radius[A] == t.radius[B] && A < B)));
+    if (split_a) {
+      sub.push_back({t.child[2 * A + 1], B});
+      sub.push_back({t.child[2 * A], B});
     } else {
-      interact(T, t.child[2 * S]);
-      interact(T, t.child[2 * S + 1]);
+      sub.push_back({A, t.child[2 * B + 1]});
+      sub.push_back({A, t.child[2 * B]});
     }
   };
-  interact(0, 0);
-  t.m2l_ptr.assign(t.nnodes + 1, 0);
-  t.m2l_src.clear();
-  std::vector<std::vector<int>> m2lt(t.nnodes);
-  for (int n = 0; n < t.nnodes; ++n) {
-    std::sort(m2l[n].begin(), m2l[n].end());
-    t.m2l_src.insert(t.m2l_src.end(), m2l[n].begin(), m2l[n].end());
-    t.m2l_ptr[n + 1] = (int)t.m2l_src.size();
-    for (int s : m2l[n]) m2lt[s].push_back(n);
+  Pairs frontier{{0, 0}}, nextf;
+  std::vector<Pairs> m2l(1), near(1);
+  while (!frontier.empty() && frontier.size() < 32768) {
+    nextf.clear();
+    for (auto [A, B] : frontier) visit(A, B, m2l[0], near[0], nextf);
+    frontier.swap(nextf);
   }
-  t.m2lt_ptr.assign(t.nnodes + 1, 0);
-  t.m2lt_tgt.clear();
-  for (int n = 0; n < t.nnodes; ++n) {
-    std::sort(m2lt[n].begin(), m2lt[n].end());
-    t.m2lt_tgt.insert(t.m2lt_tgt.end(), m2lt[n].begin(), m2lt[n].end());
-    t.m2lt_ptr[n + 1] = (int)t.m2lt_tgt.size();
-  }
-  auto by_length = [&](const std::vector<int>& ptr, std::vector<int>& ord) {
-    ord.resize(t.nnodes);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
-  };
-  by_length(t.m2l_ptr, t.m2l_order);
-  by_length(t.m2lt_ptr, t.m2lt_order);
-  t.near_ptr.assign(M + 1, 0);
-  t.near_idx.clear();
-  for (int i = 0; i < M; ++i) {
-    std::sort(near[i].begin(), near[i].end());
-    t.near_idx.insert(t.near_idx.end(), near[i].begin(), near[i].end());
-    t.near_ptr[i + 1] = (int)t.near_idx.size();
-  }
+  const long nf = (long)frontier.size();
+  const long per = 8;
+  const long nparts = (nf + per - 1) / per;
+  m2l.resize(1 + nparts);
+  near.resize(1 + nparts);
+  parallel_for(nparts, 1, [&](long k) {
+    Pairs stack;
+    for (long f = k * per; f < std::min(nf, (k + 1) * per); ++f) {
+      stack.push_back(frontier[f]);
+      while (!stack.empty()) {
+        const auto [A, B] = stack.back();
+        stack.pop_back();
+        visit(A, B, m2l[1 + k], near[1 + k], stack);
+      }
+    }
+  });
+  pairs_to_csr(m2l, t.nnodes, t.m2l_ptr, t.m2l_src);
+  pairs_to_csr(near, M, t.near_ptr, t.near_idx);
+  t.m2l_order.resize(t.nnodes);
+  std::iota(t.m2l_order.begin(), t.m2l_order.end(), 0);
+  std::stable_sort(t.m2l_order.begin(), t.m2l_order.end(), [&](int a, int b) {
+    return t.m2l_ptr[a + 1] - t.m2l_ptr[a] > t.m2l_ptr[b + 1] - t.m2l_ptr[b];
+  });
   (void)r;
 }
 
@@ -196,6 +254,13 @@ struct Tables {
   // the row t = l^2 + l + m'.
   std::vector<double> Jval;
   std::vector<int> Jrow;
+  // The same rows for the wavefront M2L kernel: row t = 64 g + lane of group g, padded
+  // with zeros to K_g entries (the largest count of the group, rounded up to even),
+  // laid out [mat][g][k][lane]; K_g in 4-bit fields of jpad_kpack.  Needs every row to
+  // be one run of step 2 (jpad_ok).
+  std::vector<double> Jpad;
+  int jpad_kpack = 0;
+  bool jpad_ok = false;
   // z-translation coefficients of the M2L kernel laid out per output pair (lo, |m|):
   // Z[kern][dir] holds for every pair the entries of l_in = |m|..p in order (Yukawa:
   // k = |m|..min(lo, l_in); Laplace: one value); dir 0 is the forward translation
@@ -331,6 +396,36 @@ inline void build_tables(int pmax, Tables& tb) {
         for (int b : cols) tb.Jval.push_back(mat == 0 ? tb.J[tb.Joff[l] + a * w + b] : tb.J[tb.Joff[l] + b * w + a]);
       }
     }
+  const int G = (L + 63) / 64;
+  std::vector<int> K(G, 0);
+  tb.jpad_ok = G <= 7;
+  for (int mat = 0; mat < 2; ++mat)
+    for (int t = 0; t < L; ++t) {
+      const int d = tb.Jrow[2 * (mat * L + t) + 1], cnt = (d >> 12) & 255, st = d >> 20;
+      if (cnt > 1 && st != 2) tb.jpad_ok = false;
+      K[t / 64] = std::max(K[t / 64], cnt);
+    }
+  tb.jpad_kpack = 0;
+  tb.Jpad.clear();
+  if (tb.jpad_ok) {
+    for (int g = 0; g < G; ++g) {
+      K[g] += K[g] & 1;
+      if (K[g] > 14) tb.jpad_ok = false;
+      tb.jpad_kpack |= K[g] << (4 * g);
+    }
+    for (int mat = 0; mat < 2; ++mat)
+      for (int g = 0; g < G; ++g)
+        for (int k = 0; k < K[g]; ++k)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int t = 64 * g + lane;
+            double v = 0.0;
+            if (t < L) {
+              const int off = tb.Jrow[2 * (mat * L + t)], cnt = (tb.Jrow[2 * (mat * L + t) + 1] >> 12) & 255;
+              if (k < cnt) v = tb.Jval[off + k];
+            }
+            tb.Jpad.push_back(v);
+          }
+  }
 }
 
 }  // namespace fmm
