@@ -552,12 +552,17 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         // k_n(z) z^n by the upward recurrence kt_{n+1} = z^2 kt_{n-1} + (2n+1) kt_n
         const double z = f.kappa * rho, z2 = z * z;
         double km = 1.5707963267948966 * exp(-z) * irho * f.kinv;
-        double kc = km * (z + 1.0), c = 3.0;
-        for (int j = 1; j < lane; ++j) {
+        double kc = km * (z + 1.0), c = 3.0;  // km = kt_{j-1}, kc = kt_j, c = 2j + 1
+        int j = 1;
+        for (; j + 1 < lane; j += 2) {
+          km = z2 * km + c * kc;
+          kc = z2 * kc + (c + 2.0) * km;
+          c += 4.0;
+        }
+        if (j < lane) {
           const double kn = z2 * km + c * kc;
           km = kc;
           kc = kn;
-          c += 2.0;
         }
         kt[lane] = lane == 0 ? km : kc;
       }
@@ -588,19 +593,25 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         const int lo = code >> 8, am = code & 255;
         const double* zp = Z + zs[2 * s + 1];
         double sp = 0.0, sm = 0.0;
+        // running quantities at degree li: ib = li^2 + li, kp = kt + lo + li - am,
+        // nk = min(lo, li) - am + 1 terms of the k-sum
+        int ib = am * am + am, di = 2 * am + 2, nk = 1;
+        const double* kp = kt + lo;
         for (int li = am; li <= p; ++li) {
           double e;
           if constexpr (YUK) {
-            const int nk = min(lo, li) - am + 1;
-            const double* kp = kt + lo + li - am;
             e = 0.0;
             for (int kk = 0; kk < nk; ++kk) e = fma(zp[kk], kp[-kk], e);
             zp += nk;
           } else {
             e = *zp++;
           }
-          sp += e * b0[li * li + li + am];
-          sm += e * b0[li * li + li - am];
+          sp = fma(e, b0[ib + am], sp);
+          sm = fma(e, b0[ib - am], sm);
+          ib += di;
+          di += 2;
+          ++kp;
+          nk += li < lo ? 1 : 0;
         }
         b1[lo * lo + lo + am] = sp;
         if (am) b1[lo * lo + lo - am] = sm;
