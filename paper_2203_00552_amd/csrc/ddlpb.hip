@@ -83,6 +83,8 @@ struct ddlpb_ctx {
   rocblas_handle blas = nullptr;
   bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
   int pkrylov = 6;            // > 0: preconditioner = this many GMRES steps on L_AB (flexible outer)
+  int solver = 0;             // 0: GMRES, 1: Jacobi-DIIS (the paper's macro/micro iterations)
+  int diis_max = 8;           // DIIS history length
   int inner_iters = 12;       // GMRES steps on the near operator P per outer iteration
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
@@ -1146,8 +1148,13 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
 // 1e-4 relative and at most one Krylov cycle each, and the refinement contracts.
 constexpr int kMaxRefine = 10;
 constexpr double kInnerFloor = 1e-4;
+int diis_solve(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres);
 int solve_system(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
   c->cur_prec = 0;
+  if (c->solver == 1) {  // Jacobi-DIIS, FP64
+    c->stats.refinements = 0;
+    return diis_solve(c, transpose, b, x, tol, iters, relres);
+  }
   if (c->precision != 2 || !c->use_caps || !c->d_rr) {
     c->stats.refinements = 0;
     return gmres(c, transpose, b, x, tol, iters, relres);
@@ -1187,6 +1194,162 @@ int solve_system(ddlpb_ctx* c, bool transpose, const double* b, double* x, doubl
   *iters = total;
   *relres = rel;
   return rel <= tol ? DDLPB_OK : DDLPB_ENOCONV;
+}
+
+// ------------------------------------------------------ Jacobi-DIIS solver
+// max |a - b| and max |s + a| over the 2ML entries (null b or s: that term is |a|)
+void amax2(ddlpb_ctx* c, const double* a, const double* b, const double* s, double* m1, double* m2) {
+  const long D = 2L * c->M * c->L;
+  hipLaunchKernelGGL(k_amax2, dim3(c->nb_dot), dim3(256), 0, c->stream, D, a, b, s, c->d_part);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(2 * (size_t)c->nb_dot);
+  HIPCHK(hipMemcpyAsync(h.data(), c->d_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *m1 = *m2 = 0.0;
+  for (int k = 0; k < c->nb_dot; ++k) {
+    *m1 = std::max(*m1, h[2 * k]);
+    *m2 = std::max(*m2, h[2 * k + 1]);
+  }
+}
+
+// DIIS (Pulay) extrapolation for a fixed point x = F(x): keeps the last m values
+// f_i = F(x_i) and errors e_i = f_i - x_i on the device (slots F[i], E[i], stride D),
+// their Gram matrix on the host, and returns sum_i c_i f_i with sum_i c_i = 1
+// minimising |sum_i c_i e_i| (Pulay 1980).
+struct Diis {
+  ddlpb_ctx* c;
+  double *F, *E;
+  int m, count = 0, head = 0;
+  std::vector<double> B;  // [m][m] Gram matrix of the error slots
+  Diis(ddlpb_ctx* c_, double* F_, double* E_, int m_) : c(c_), F(F_), E(E_), m(m_), B((size_t)m_ * m_, 0.0) {}
+  void reset() { count = head = 0; }
+  // slot for the next pair (the caller writes f and e there), then push() records it
+  double* fslot() { return F + (long)head * 2L * c->M * c->L; }
+  double* eslot() { return E + (long)head * 2L * c->M * c->L; }
+  void push() {
+    const long D = 2L * c->M * c->L;
+    const int n = std::min(count + 1, m);
+    std::vector<double> h(n);
+    mdot(c, n, E, D, eslot(), h.data());
+    for (int i = 0; i < n; ++i) B[(size_t)head * m + i] = B[(size_t)i * m + head] = h[i];
+    count = n;
+    head = (head + 1) % m;
+  }
+  // x = sum c_i f_i; false when the bordered system is singular (x untouched)
+  bool extrapolate(double* x) {
+    const int n = count, A = n + 1;
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = std::max(scale, B[(size_t)i * m + i]);
+    if (!(scale > 0.0)) return false;
+    std::vector<double> G((size_t)A * A, 0.0), r(A, 0.0);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) G[(size_t)i * A + j] = B[(size_t)i * m + j] / scale;
+      G[(size_t)i * A + n] = G[(size_t)n * A + i] = 1.0;
+    }
+    r[n] = 1.0;
+    for (int k = 0; k < A; ++k) {  // Gaussian elimination, partial pivoting
+      int piv = k;
+      for (int i = k + 1; i < A; ++i)
+        if (std::fabs(G[(size_t)i * A + k]) > std::fabs(G[(size_t)piv * A + k])) piv = i;
+      if (std::fabs(G[(size_t)piv * A + k]) < 1e-14) return false;
+      if (piv != k) {
+        for (int j = 0; j < A; ++j) std::swap(G[(size_t)k * A + j], G[(size_t)piv * A + j]);
+        std::swap(r[k], r[piv]);
+      }
+      for (int i = k + 1; i < A; ++i) {
+        const double f = G[(size_t)i * A + k] / G[(size_t)k * A + k];
+        for (int j = k; j < A; ++j) G[(size_t)i * A + j] -= f * G[(size_t)k * A + j];
+        r[i] -= f * r[k];
+      }
+    }
+    std::vector<double> cf(A);
+    for (int i = A - 1; i >= 0; --i) {
+      double v = r[i];
+      for (int j = i + 1; j < A; ++j) v -= G[(size_t)i * A + j] * cf[j];
+      cf[i] = v / G[(size_t)i * A + i];
+    }
+    const long D = 2L * c->M * c->L;
+    HIPCHK(hipMemcpyAsync(c->d_hv, cf.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, n, F, D, c->d_hv, x);
+    HIPCHK(hipGetLastError());
+    return true;
+  }
+};
+
+// The paper's solver (Sec. 5, opening): macro-iterations X <- L_AB^{-1}(g - L_C X)
+// accelerated by DIIS, L_AB being the preconditioner; each L_AB solve by
+// micro-iterations (Jacobi sweeps X <- b + (I - L_AB) X, the diagonal blocks being
+// the identity, also accelerated by DIIS) started from the previous macro iterate,
+// i.e. the correction d of L_AB d = g - L X starts from zero.  Both stop on the
+// relative infinity-norm increment: tol for the macro, tol / 100 for the micro
+// iterations.  relres reports the final ||g - L X|| / ||g||.
+int diis_solve(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, int* iters, double* relres) {
+  const long D = 2L * c->M * c->L;
+  const int m = std::min(c->diis_max, (c->restart + 1 - 4) / 4);
+  *iters = 0;
+  *relres = 0.0;
+  if (m < 2) return DDLPB_EINVAL;
+  const double bn = norm2(c, b);
+  if (bn == 0.0) { fill(c, x, D, 0.0); return DDLPB_OK; }
+  double* V = c->d_V;
+  Diis mac(c, V, V + (long)m * D, m), mic(c, V + 2L * m * D, V + 3L * m * D, m);
+  double* r = V + 4L * m * D;  // g - L X
+  double* d = r + D;           // micro iterate (correction)
+  double* dn = d + D;          // Jacobi image of d
+  auto op = [&](const double* in, double* out) { if (transpose) op_LT(c, in, out); else op_L(c, in, out); };
+  auto sweep = [&](const double* rhs, const double* z, double* out) {  // rhs + (I - L_AB) z
+    if (!transpose) {
+      apply_LX(c, rhs, 1.0, z, 1.0, nullptr, nullptr, nullptr, 0.0, out);
+    } else {
+      syn2(c, z, 0, c->d_zr, c->d_ze);
+      apply_LTZ(c, rhs, 1.0, c->d_zr, c->d_ze, 1.0, nullptr, 0, out);
+    }
+  };
+  const double tin = tol / 100.0;
+  bool conv = false;
+  int it = 0;
+  for (; it < c->maxit && !conv; ++it) {
+    op(x, c->d_w);
+    HIPCHK(hipMemcpyAsync(r, b, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    axpby(c, -1.0, c->d_w, 1.0, r);
+    // micro-iterations on L_AB d = r from d = 0 (first Jacobi image: d = r)
+    mic.reset();
+    HIPCHK(hipMemcpyAsync(d, r, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    for (int mi = 0; mi < 200; ++mi) {
+      sweep(r, d, dn);
+      c->inner_total += 1;
+      double inc, nrm;
+      amax2(c, dn, d, x, &inc, &nrm);
+      if (inc <= tin * nrm) {
+        HIPCHK(hipMemcpyAsync(d, dn, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        break;
+      }
+      HIPCHK(hipMemcpyAsync(mic.fslot(), dn, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(mic.eslot(), dn, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      axpby(c, -1.0, d, 1.0, mic.eslot());
+      mic.push();
+      if (!mic.extrapolate(d)) HIPCHK(hipMemcpyAsync(d, dn, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    // macro fixed point: F(X) = X + d
+    double inc, nrm;
+    amax2(c, d, nullptr, x, &inc, &nrm);
+    if (inc <= tol * nrm) conv = true;
+    HIPCHK(hipMemcpyAsync(mac.fslot(), x, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    axpby(c, 1.0, d, 1.0, mac.fslot());
+    HIPCHK(hipMemcpyAsync(mac.eslot(), d, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (conv) {
+      HIPCHK(hipMemcpyAsync(x, mac.fslot(), D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    }
+    mac.push();
+    if (!mac.extrapolate(x)) axpby(c, 1.0, d, 1.0, x);
+  }
+  op(x, c->d_w);
+  HIPCHK(hipMemcpyAsync(r, b, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  axpby(c, -1.0, c->d_w, 1.0, r);
+  *relres = norm2(c, r) / bn;
+  *iters = conv ? it + 1 : it;
+  return conv ? DDLPB_OK : DDLPB_ENOCONV;
 }
 
 // ------------------------------------------------------------ device setup
@@ -1730,6 +1893,12 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (!(v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
     c->m2l_cfg[0].valid = c->m2l_cfg[1].valid = false;
+  } else if (k == "solver") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->solver = (int)v;
+  } else if (k == "diis_max") {
+    if (!(v >= 2 && v <= 32)) return DDLPB_EINVAL;
+    c->diis_max = (int)v;
   } else if (k == "theta") {
     if (fixed) return DDLPB_ESTATE;
     if (!(v > 0 && v < 1)) return DDLPB_EINVAL;

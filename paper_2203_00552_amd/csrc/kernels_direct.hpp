@@ -661,6 +661,33 @@ __global__ void k_axpby(long D, double a, const double* __restrict__ x, double b
   if (k < D) y[k] = a * x[k] + b * y[k];
 }
 // y = sum_v V[v] c[v]
+// Per-block maxima of |a - b| (b may be null: |a|) and |s + a| (s may be null: |a|):
+// part[2 block], part[2 block + 1]; grid-stride, 256 threads.
+__global__ __launch_bounds__(256) void k_amax2(long D, const double* __restrict__ a, const double* __restrict__ b,
+                                               const double* __restrict__ s, double* __restrict__ part) {
+  __shared__ double sh[2][256];
+  double m1 = 0.0, m2 = 0.0;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < D; k += 256L * gridDim.x) {
+    const double av = a[k];
+    m1 = fmax(m1, fabs(b ? av - b[k] : av));
+    m2 = fmax(m2, fabs(s ? s[k] + av : av));
+  }
+  sh[0][threadIdx.x] = m1;
+  sh[1][threadIdx.x] = m2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+      sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
 __global__ void k_mcomb(long D, int nv, const double* __restrict__ V, long ldv, const double* __restrict__ c,
                         double* __restrict__ y) {
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
