@@ -158,6 +158,13 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "max_iter"       maximal GMRES iterations per solve
  *   "leaf_size"      maximal spheres per FMM tree leaf
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
+ *   "solver"         0 (default): GMRES as above; 1: the Jacobi-DIIS scheme of
+ *                    Sec. 5 (macro-iterations X <- X + L_AB^-1 (g - L X) with DIIS,
+ *                    L_AB^-1 by DIIS-accelerated Jacobi micro-iterations, both
+ *                    stopping on the relative infinity-norm increment, tol and
+ *                    tol/100; FP64; stats report the final relative residual)
+ *   "diis_max"       DIIS history length (2..32, default 8; at most
+ *                    (gmres_restart - 3) / 4, the histories use the GMRES basis)
  *   "warm_start"     1 (default): solves start from the previous X / X_adj;
  *                    0: every solve starts from zero
  *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field kernels of the mixed
