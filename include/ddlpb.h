@@ -115,6 +115,25 @@ int ddlpb_adjoint(ddlpb_ctx* ctx, double tol);
 int ddlpb_forces(ddlpb_ctx* ctx, double* forces_out);
 
 /*
+ * ddlpb_eval_potentials -- the reaction and extended potentials at arbitrary
+ * points from the solved expansions (Sec. 2: psi_r(x) = sum_lm X_r,ilm
+ * (|x - x_i|/r_i)^l Y_lm and psi_e(x) = sum_lm X_e,ilm i_l(kappa|x - x_i|) /
+ * i_l(kappa r_i) Y_lm for x in the ball i), with their gradients; -grad psi_r is
+ * the reaction field, e.g. for coupling to QM or polarisable models.
+ *   points  [n][3] host, Angstrom
+ *   spheres [n] host: the ball whose expansion each point uses (0..M-1), or NULL
+ *           for the ball with the smallest |x - x_i| / r_i (a ball containing
+ *           the point when there is one; found by scanning all M spheres)
+ *   out     [n][8] host, caller-owned: psi_r, psi_e, d psi_r / dx,y,z,
+ *           d psi_e / dx,y,z (e / Angstrom, e / Angstrom^2)
+ * Requires a prior ddlpb_solve.  Allocates a temporary device block of 92 bytes
+ * per point.  Errors: EINVAL (n < 0, null pointers, non-finite points, ball index
+ * out of range), ESTATE, ENOMEM.
+ */
+int ddlpb_eval_potentials(ddlpb_ctx* ctx, int32_t n_points, const double* points, const int32_t* spheres,
+                          double* out);
+
+/*
  * ddlpb_charge_gradient -- dE_s/dq_k for every atom, written to dedq_out [M]
  * (host, e/Angstrom).  The adjoint solution gives the derivative with respect to
  * any parameter of the system at no further solve (Sec. 3, adjoint method):

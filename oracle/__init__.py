@@ -159,6 +159,50 @@ class Problem:
         _load().oracle_forces_from(*self._args(), _ptr(X), _ptr(Xa), _ptr(F))
         return F
 
+    def potentials(self, X, points, spheres=None, h=1e-4):
+        """Reaction and extended potentials at points from the expansions of a ball
+        (Sec. 2, the representation of psi_r and psi_e once X is known):
+            psi_r(x) = sum_lm X_r,ilm (|x - x_i| / r_i)^l Y_lm(x - x_i),
+            psi_e(x) = sum_lm X_e,ilm i_l(kappa |x - x_i|) / i_l(kappa r_i) Y_lm(x - x_i),
+        written out term by term; the gradients are central differences of the same
+        sums with step h r_i.  spheres None: the ball with the smallest |x - x_i| / r_i.
+        Returns psi_r [n], psi_e [n], grad psi_r [n, 3], grad psi_e [n, 3]."""
+        X = np.asarray(X, dtype=np.float64).reshape(2, self.M, self.L)
+        pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+        if spheres is None:
+            d2 = ((pts[:, None, :] - self.x[None, :, :]) ** 2).sum(-1) / self.r[None, :] ** 2
+            spheres = d2.argmin(axis=1)
+        lmax = self.lmax
+        deg = np.repeat(np.arange(lmax + 1), 2 * np.arange(lmax + 1) + 1)
+
+        def values(x, i):
+            v = x - self.x[i]
+            d = float(np.sqrt(v @ v))
+            ir = bessel(lmax, self.kappa * self.r[i])[0]
+            if d == 0.0:  # only l = 0 survives: Y_00 = 1 / sqrt(4 pi), i_0(0) = 1
+                y00 = 1.0 / np.sqrt(4.0 * np.pi)
+                return X[0, i, 0] * y00, X[1, i, 0] * y00 / ir[0]
+            Y = sph_harm(lmax, v)[0]
+            rad_r = (d / self.r[i]) ** deg
+            rad_e = (bessel(lmax, self.kappa * d)[0] / ir)[deg]
+            return float((X[0, i] * rad_r * Y).sum()), float((X[1, i] * rad_e * Y).sum())
+
+        n = pts.shape[0]
+        pr, pe = np.zeros(n), np.zeros(n)
+        gr, ge = np.zeros((n, 3)), np.zeros((n, 3))
+        for k in range(n):
+            i = int(spheres[k])
+            pr[k], pe[k] = values(pts[k], i)
+            step = h * self.r[i]
+            for c in range(3):
+                e = np.zeros(3)
+                e[c] = step
+                a = values(pts[k] + e, i)
+                b = values(pts[k] - e, i)
+                gr[k, c] = (a[0] - b[0]) / (2 * step)
+                ge[k, c] = (a[1] - b[1]) / (2 * step)
+        return pr, pe, gr, ge
+
     def charge_gradient(self, method="auto", tol=1e-12):
         """dE/dq_k for every atom.  E is a quadratic form in the charges (g and Q are
         linear in q, Sec. 2.2 and 3), so the central difference with unit step,

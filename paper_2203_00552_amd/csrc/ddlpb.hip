@@ -1793,6 +1793,51 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
   });
 }
 
+int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
+                          double* out) {
+  if (!c || n_points < 0 || (n_points > 0 && (!points || !out))) return DDLPB_EINVAL;
+  if (c->state < 1) return DDLPB_ESTATE;
+  for (long k = 0; k < 3L * n_points; ++k)
+    if (!std::isfinite(points[k])) return DDLPB_EINVAL;
+  if (spheres)
+    for (int k = 0; k < n_points; ++k)
+      if (spheres[k] < 0 || spheres[k] >= c->M) return DDLPB_EINVAL;
+  if (n_points == 0) return DDLPB_OK;
+  return guarded([&]() -> int {
+    // points, balls and results in one temporary device block (freed before return)
+    const size_t bp = 3L * n_points * sizeof(double), bo = 8L * n_points * sizeof(double);
+    const size_t bb = ((size_t)n_points * sizeof(int) + 255) / 256 * 256;
+    char* blk = nullptr;
+    if (hipMalloc((void**)&blk, bp + bo + bb) != hipSuccess) { (void)hipGetLastError(); return DDLPB_ENOMEM; }
+    double* dp = (double*)blk;
+    double* dout = (double*)(blk + bp);
+    int* dball = (int*)(blk + bp + bo);
+    int rc = DDLPB_OK;
+    try {
+      HIPCHK(hipMemcpyAsync(dp, points, bp, hipMemcpyHostToDevice, c->stream));
+      if (spheres) {
+        HIPCHK(hipMemcpyAsync(dball, spheres, (size_t)n_points * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      } else {
+        hipLaunchKernelGGL(k_nearest_ball, dim3(nblk(n_points, 256)), dim3(256), 0, c->stream, n_points, dp, c->M,
+                           c->d_xyz, c->d_rad, dball);
+        HIPCHK(hipGetLastError());
+      }
+      LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eval_points<LMc>), dim3(nblk(n_points, 256)), dim3(256), 0,
+                                              c->stream, n_points, dp, dball, c->M, c->L, c->LUR, c->d_X, c->d_xyz,
+                                              c->d_rad, c->d_isgr, c->kappa, c->nterms, dout));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(out, dout, bo, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(blk);
+      throw;
+    }
+    HIPCHK(hipFree(blk));
+    return rc;
+  });
+}
+
 int ddlpb_charge_gradient(ddlpb_ctx* c, double* dedq_out) {
   if (!c || !dedq_out) return DDLPB_EINVAL;
   if (c->state < 2) return DDLPB_ESTATE;

@@ -338,4 +338,72 @@ __global__ void k_force_final(int M, const int* __restrict__ nptr, const int* __
   }
 }
 
+// ------------------------------------------- potentials at arbitrary points
+// Ball of a point: the sphere i with the smallest |x - x_i| / r_i (so a point of the
+// cavity gets a ball that contains it).  One thread per point, all spheres scanned.
+__global__ __launch_bounds__(256) void k_nearest_ball(int n, const double* __restrict__ pts, int M,
+                                                      const double* __restrict__ xyz, const double* __restrict__ rad,
+                                                      int* __restrict__ ball) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double px = pts[3 * k], py = pts[3 * k + 1], pz = pts[3 * k + 2];
+  double best = 1e300;
+  int bi = 0;
+  for (int i = 0; i < M; ++i) {
+    const double dx = px - xyz[3 * i], dy = py - xyz[3 * i + 1], dz = pz - xyz[3 * i + 2];
+    const double s = (dx * dx + dy * dy + dz * dz) / (rad[i] * rad[i]);
+    if (s < best) { best = s; bi = i; }
+  }
+  ball[k] = bi;
+}
+
+// Reaction and extended potentials from the expansions of ball i = ball[k] (Sec. 2):
+//   psi_r(x) = sum_lm X_r,ilm (|x - x_i| / r_i)^l Y_lm,
+//   psi_e(x) = sum_lm X_e,ilm i_l(kappa |x - x_i|) / i_l(kappa r_i) Y_lm,
+// and their gradients (dual numbers in x).  out[k][8] = psi_r, psi_e, grad psi_r,
+// grad psi_e.  With v = (x - x_i)/r_i the first basis is the solid harmonic S_lm(v)
+// and the second sigma_l(kappa^2 r_i^2 |v|^2) / sigma_l(kappa^2 r_i^2) S_lm(v).
+template <int LM>
+__global__ __launch_bounds__(256) void k_eval_points(int n, const double* __restrict__ pts, const int* __restrict__ ball,
+                                                     int M, int L, int LUR, const double* __restrict__ X,
+                                                     const double* __restrict__ xyz, const double* __restrict__ rad,
+                                                     const double* __restrict__ isgr, double kappa, int nterms,
+                                                     double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = ball[k];
+  const double ri = rad[i], iri = 1.0 / ri;
+  using D = Dual<double>;
+  D v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    v[c] = D(pts[3 * k + c]);
+    v[c].g[c] = 1.0;
+    v[c] = (v[c] - D(xyz[3 * i + c])) * iri;
+  }
+  D z2 = (kappa * kappa * ri * ri) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  D sg[LM + 1];
+  sigma_weights<LM, D>(z2, nterms, sg);
+  const double* Xr = X + (long)i * L;
+  const double* Xe = X + (long)(M + i) * L;
+  D sa(0.0), pb[LM + 1];
+#pragma unroll
+  for (int l = 0; l <= LM; ++l) pb[l] = D(0.0);
+  for_each_solid_harmonic<LM, D>(v[0], v[1], v[2], [&](int l, int idx, const D& S) {
+    sa = sa + Xr[idx] * S;
+    pb[l] = pb[l] + Xe[idx] * S;
+  });
+  D sb(0.0);
+#pragma unroll
+  for (int l = 0; l <= LM; ++l) sb = sb + isgr[(long)i * LUR + l] * (pb[l] * sg[l]);
+  double* o = out + 8L * k;
+  o[0] = sa.v;
+  o[1] = sb.v;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o[2 + c] = sa.g[c];
+    o[5 + c] = sb.g[c];
+  }
+}
+
 }  // namespace ddlpb

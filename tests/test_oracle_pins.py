@@ -311,3 +311,62 @@ def test_charge_gradient_euler_and_small_step():
         em = P.solve("dense", forces=False)["energy"]
         P.q = q0
         assert abs((ep - em) / (2 * h) - g[k]) < 1e-9 * np.abs(g).max()
+
+
+# ------------------------------------------------ potentials at points (Sec. 2)
+def _solved_small():
+    x, r, q = inputs.small_cluster(0)
+    P = oracle.Problem(x, r, q, lmax=6, n_lebedev=110)
+    return P, P.solve("dense"), x, r, q
+
+
+def test_potentials_energy_identity():
+    """E = 1/2 sum_j q_j psi_r(x_j): the reaction potential of each ball at its own
+    centre gives the energy of the solve (Sec. 3 energy equation)."""
+    P, ref, x, r, q = _solved_small()
+    pr, pe, gr, ge = P.potentials(ref["X"], x, spheres=np.arange(len(r)))
+    assert abs(0.5 * (q * pr).sum() / ref["energy"] - 1) < 1e-12
+
+
+def test_potentials_on_the_sphere():
+    """On the sphere |x - x_i| = r_i both radial factors are 1, so psi_r and psi_e are
+    the harmonic syntheses of X_r,i and X_e,i at the Lebedev directions."""
+    P, ref, x, r, q = _solved_small()
+    X = np.asarray(ref["X"]).reshape(2, P.M, P.L)
+    s = oracle.lebedev(110)[0]
+    i = 3
+    pts = x[i] + r[i] * s
+    pr, pe, _, _ = P.potentials(X, pts, spheres=np.full(len(s), i))
+    Y = oracle.sph_harm(6, s)
+    assert np.abs(pr - Y @ X[0, i]).max() < 1e-12 * np.abs(Y @ X[0, i]).max()
+    assert np.abs(pe - Y @ X[1, i]).max() < 1e-12 * np.abs(Y @ X[1, i]).max()
+
+
+def test_potentials_solve_their_equations():
+    """Inside a ball psi_r is harmonic and psi_e solves (Laplace - kappa^2) psi_e = 0
+    (the two equations of Sec. 2); checked with a second-difference Laplacian, and
+    the returned gradients against a wider central difference."""
+    P, ref, x, r, q = _solved_small()
+    i = 5
+    c = x[i] + 0.37 * r[i] * np.array([0.6, -0.48, 0.64])
+    h = 2e-3 * r[i]
+    offs = [np.zeros(3)] + [s * h * e for e in np.eye(3) for s in (1, -1)]
+    pr, pe, gr, ge = P.potentials(ref["X"], np.array([c + o for o in offs]), spheres=np.full(7, i))
+    lap_r = (pr[1:].sum() - 6 * pr[0]) / h ** 2
+    lap_e = (pe[1:].sum() - 6 * pe[0]) / h ** 2
+    scale_r = np.abs(gr[0]).max() / r[i]
+    scale_e = np.abs(ge[0]).max() / r[i]
+    assert abs(lap_r) < 1e-4 * scale_r
+    assert abs(lap_e - P.kappa ** 2 * pe[0]) < 1e-4 * scale_e + 1e-4 * P.kappa ** 2 * abs(pe[0])
+    fd_r = np.array([(pr[1 + 2 * k] - pr[2 + 2 * k]) / (2 * h) for k in range(3)])
+    assert np.abs(fd_r - gr[0]).max() < 1e-5 * np.abs(gr[0]).max()
+
+
+def test_potentials_regular_at_the_centre():
+    """Both expansions are regular at the ball centre (r^l and i_l, not r^-(l+1) or
+    k_l): values 1e-6 r_i away from the centre match the centre values."""
+    P, ref, x, r, q = _solved_small()
+    i = 7
+    pts = np.array([x[i], x[i] + 1e-6 * r[i] * np.array([0.0, 0.6, 0.8])])
+    pr, pe, _, _ = P.potentials(ref["X"], pts, spheres=[i, i])
+    assert abs(pr[1] - pr[0]) < 1e-5 * abs(pr[0]) and abs(pe[1] - pe[0]) < 1e-5 * abs(pe[0])
