@@ -829,24 +829,44 @@ void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx,
   }
   HIPCHK(hipGetLastError());
 }
+// blocks of a level pass: one wavefront per node, at most 8 blocks per compute unit
+inline int level_blocks(int cnt) { return std::max(1, std::min((cnt + kLevelWaves - 1) / kLevelWaves, 2048)); }
+// LDS layout of the level passes: the coefficient table is staged when table and
+// scratch fit in 150 KB; the kernels are allowed the dynamic size they need
+void level_lds(ddlpb_ctx* c, const FmmDev& f, int& stage, size_t& bytes) {
+  stage = level_lds_bytes(f.kernel, f.p, f.nA, 1) <= 150 * 1024 ? 1 : 0;
+  bytes = level_lds_bytes(f.kernel, f.p, f.nA, stage);
+  if (bytes > 65536) {
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fmm_upward), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fmm_downward),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fmm_upward_T),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  }
+  (void)c;
+}
 // sphere locals SL [M][P] of the far field of per-sphere sources src (degree ps, stride lds)
 void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, double* SL) {
   const auto& t = c->tree;
   const int p = c->fmm_order, P = (p + 1) * (p + 1);
   FmmDev f = fmm_dev(c, kernel);
+  int stage = 0;
+  size_t lb = 0;
+  level_lds(c, f, stage, lb);
   KScope ks(c, kernel == 0 ? "pass_fmm_yukawa" : "pass_fmm_laplace",
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, ps, lds, c->d_sleaf, src, c->d_Mn);
   for (int lev = t.nlevels - 2; lev >= 0; --lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_upward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
-                       c->d_fchild, c->d_Mn);
+    hipLaunchKernelGGL(k_fmm_upward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
+                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fchild, stage, c->d_Mn);
   }
   launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 0, c->d_Mn, c->d_Ln);
   for (int lev = 1; lev < t.nlevels; ++lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
-                       c->d_fparent, 0, c->d_Ln);
+    hipLaunchKernelGGL(k_fmm_downward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
+                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fparent, 0, stage, c->d_Ln);
   }
   hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, c->d_Ln, 0, SL);
   HIPCHK(hipGetLastError());
@@ -856,20 +876,23 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
   const auto& t = c->tree;
   const int p = c->fmm_order, P = (p + 1) * (p + 1);
   FmmDev f = fmm_dev(c, kernel);
+  int stage = 0;
+  size_t lb = 0;
+  level_lds(c, f, stage, lb);
   KScope ks(c, kernel == 0 ? "pass_fmm_yukawa_T" : "pass_fmm_laplace_T",
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   fill(c, c->d_Ln, (long)t.nnodes * P, 0.0);
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, Lam, c->d_Ln);
   for (int lev = t.nlevels - 2; lev >= 0; --lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_upward_T, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
-                       c->d_fchild, c->d_Ln);
+    hipLaunchKernelGGL(k_fmm_upward_T, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
+                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fchild, stage, c->d_Ln);
   }
   launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 1, c->d_Ln, c->d_Mn);  // symmetric lists: by source
   for (int lev = 1; lev < t.nlevels; ++lev) {
     const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_downward, dim3(cnt), dim3(64), 0, c->stream, f, c->d_flevn + t.level_ptr[lev], cnt,
-                       c->d_fparent, 1, c->d_Mn);
+    hipLaunchKernelGGL(k_fmm_downward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
+                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fparent, 1, stage, c->d_Mn);
   }
   hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, pd, ldd, c->d_sleaf, c->d_Mn,
                      accumulate, out);

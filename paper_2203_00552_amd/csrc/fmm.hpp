@@ -42,6 +42,30 @@ struct FmmDev {
   double kinv;           // 1 / kappa
 };
 
+// The same scratch as pointers into dynamic LDS, sized for the tree's order p
+struct TransView {
+  double *b0, *b1, *bes, *pw1, *pw2, *radS, *radT, *cph, *sph, *cth, *sth;
+};
+__host__ __device__ constexpr int trans_view_doubles(int p) {
+  return 3 * (p + 1) * (p + 1) + 3 * (2 * p + 4) + 2 * (p + 2) + 4 * (p + 1);  // incl. the accumulator
+}
+// carve the view (and the accumulator, returned) from `base`
+__device__ __forceinline__ double* carve_trans_view(double* base, int p, TransView& v) {
+  const int P = (p + 1) * (p + 1);
+  v.b0 = base;
+  v.b1 = v.b0 + P;
+  v.bes = v.b1 + P;
+  v.pw1 = v.bes + (2 * p + 4);
+  v.pw2 = v.pw1 + (2 * p + 4);
+  v.radS = v.pw2 + (2 * p + 4);
+  v.radT = v.radS + (p + 2);
+  v.cph = v.radT + (p + 2);
+  v.sph = v.cph + (p + 1);
+  v.cth = v.sph + (p + 1);
+  v.sth = v.cth + (p + 1);
+  return v.sth + (p + 1);  // accumulator, P entries
+}
+
 struct TransScratch {
   double b0[kPFmm], b1[kPFmm];
   double bes[2 * kPmaxFmm + 4];
@@ -155,9 +179,9 @@ __device__ __forceinline__ void zrot_table(double* c, int pdeg, const double* co
 // larger block) calls it with all lanes.  The per-translation tables (Bessel
 // values, powers, node scales, cos/sin of m*phi and m*theta as powers of the unit
 // complex numbers of the centre offset) are computed one entry per lane.
-template <bool WAVE>
-__device__ void translate(const FmmDev& f, const double* __restrict__ Atab, int kind, int S, int T, int ps, int pt,
-                          int transposed, TransScratch& sc, double* acc) {
+template <bool WAVE, class SC>
+__device__ void translate(const FmmDev& f, const double* __restrict__ Atab, const int* __restrict__ Aoff, int kind,
+                          int S, int T, int ps, int pt, int transposed, SC& sc, double* acc) {
   const int lane = tlane<WAVE>();
   const int P1 = f.p + 1;
   const int nmax = ps + pt;
@@ -245,7 +269,7 @@ __device__ void translate(const FmmDev& f, const double* __restrict__ Atab, int 
       const int lp = transposed ? li : lo;  // target degree
       double e;
       if (f.kernel == 0) {
-        const double* Ar = Atab + f.Aoff[((size_t)l * P1 + lp) * P1 + am] - am;
+        const double* Ar = Atab + Aoff[((size_t)l * P1 + lp) * P1 + am] - am;
         double sk = 0.0;
         const int kmax = min(l, lp);
         if (kind == 1) {
@@ -324,23 +348,68 @@ __global__ void k_fmm_leaf_get(int M, int p, int pd, int ldd, const int* __restr
   }
 }
 
-// upward pass of one level: M[n] = sum_children M2M(child -> n) M[child]  (internal nodes only)
-__global__ __launch_bounds__(64) void k_fmm_upward(FmmDev f, const int* __restrict__ nodes, int count,
-                                                   const int* __restrict__ child, double* __restrict__ E) {
-  __shared__ TransScratch sc;
-  __shared__ double acc[kPFmm];
-  const int n = nodes[blockIdx.x];
-  if (child[2 * n] < 0) return;  // leaf: already set (uniform for the block)
-  const int P = (f.p + 1) * (f.p + 1);
-  for (int t = threadIdx.x; t < P; t += blockDim.x) acc[t] = 0.0;
-  for (int c = 0; c < 2; ++c) {
-    const int ch = child[2 * n + c];
-    __syncthreads();
-    for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
-    __syncthreads();
-    translate<false>(f, coef_table(f, 0), 0, ch, n, f.p, f.p, 0, sc, acc);
+// Level passes: kLevelWaves wavefronts per block, each translating one node at a
+// time (grid-stride over the level's nodes); the block stages the coefficient table
+// of its translation kind (and, for Yukawa, the offsets of the packed table) in LDS
+// once.  Dynamic LDS: level_lds_bytes().
+constexpr int kLevelWaves = 8;
+__host__ __device__ inline size_t level_table_doubles(int kernel, int p, int nA) {
+  const size_t P1 = p + 1, P3 = P1 * P1 * P1;
+  return kernel == 0 ? (size_t)nA + (P3 + 1) / 2 : P3;  // Yukawa: table, then the int offsets
+}
+__host__ __device__ inline size_t level_lds_bytes(int kernel, int p, int nA, int stage) {
+  return ((stage ? level_table_doubles(kernel, p, nA) : 0) + (size_t)kLevelWaves * trans_view_doubles(p)) *
+         sizeof(double);
+}
+__device__ __forceinline__ void stage_level_table(const FmmDev& f, int kind, int stage, double* tab, const double*& At,
+                                                  const int*& Ao) {
+  const int P1 = f.p + 1, P3 = P1 * P1 * P1;
+  if (!stage) {  // table too large for LDS: read it from global memory
+    At = coef_table(f, kind);
+    Ao = f.Aoff;
+    return;
   }
-  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] = acc[t];
+  if (f.kernel == 0) {
+    int* off = (int*)(tab + f.nA);
+    for (int t = threadIdx.x; t < f.nA; t += blockDim.x) tab[t] = f.A[t];
+    for (int t = threadIdx.x; t < P3; t += blockDim.x) off[t] = f.Aoff[t];
+    Ao = off;
+  } else {
+    const double* src = f.AL + (size_t)kind * P3;
+    for (int t = threadIdx.x; t < P3; t += blockDim.x) tab[t] = src[t];
+    Ao = f.Aoff;  // unused by the Laplace translations
+  }
+  At = tab;
+  __syncthreads();
+}
+
+// upward pass of one level: M[n] = sum_children M2M(child -> n) M[child]  (internal nodes only)
+__global__ __launch_bounds__(64 * kLevelWaves) void k_fmm_upward(FmmDev f, const int* __restrict__ nodes, int count,
+                                                                 const int* __restrict__ child, int stage,
+                                                                 double* __restrict__ E) {
+  extern __shared__ double lvl_tab[];
+  const double* At;
+  const int* Ao;
+  stage_level_table(f, 0, stage, lvl_tab, At, Ao);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TransView sc;
+  double* acc = carve_trans_view(
+      lvl_tab + (stage ? level_table_doubles(f.kernel, f.p, f.nA) : 0) + (size_t)w * trans_view_doubles(f.p), f.p, sc);
+  const int P = (f.p + 1) * (f.p + 1);
+  for (int b = blockIdx.x * kLevelWaves + w; b < count; b += gridDim.x * kLevelWaves) {
+    const int n = nodes[b];
+    if (child[2 * n] < 0) continue;  // leaf: already set (uniform for the wavefront)
+    for (int t = lane; t < P; t += 64) acc[t] = 0.0;
+    for (int c = 0; c < 2; ++c) {
+      const int ch = child[2 * n + c];
+      tsync<true>();
+      for (int t = lane; t < P; t += 64) sc.b0[t] = E[(long)ch * P + t];
+      tsync<true>();
+      translate<true>(f, At, Ao, 0, ch, n, f.p, f.p, 0, sc, acc);
+    }
+    for (int t = lane; t < P; t += 64) E[(long)n * P + t] = acc[t];
+    tsync<true>();
+  }
 }
 
 // multipole-to-local: L[T] = sum_{S in list(T)} M2L(S -> T) M[S]  (every node, lists by target)
@@ -358,8 +427,8 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmDev f, int nn, const int* __r
       __syncthreads();
       for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = Ein[(long)o * P + t];
       __syncthreads();
-      if (!transposed) translate<false>(f, coef_table(f, 1), 1, o, n, f.p, f.p, 0, sc, acc);
-      else translate<false>(f, coef_table(f, 1), 1, n, o, f.p, f.p, 1, sc, acc);
+      if (!transposed) translate<false>(f, coef_table(f, 1), f.Aoff, 1, o, n, f.p, f.p, 0, sc, acc);
+      else translate<false>(f, coef_table(f, 1), f.Aoff, 1, n, o, f.p, f.p, 1, sc, acc);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < P; t += blockDim.x) Eout[(long)n * P + t] = acc[t];
@@ -651,40 +720,59 @@ inline size_t m2l_fast_lds_bytes(int p, int nZ, int njpad, int nslot, int nw, bo
 
 // downward pass of one level: L[n] += L2L(parent -> n) L[parent]
 // transposed downward (adjoint of the upward pass): Mu[n] += M2M(n -> parent)^T Mu[parent]
-__global__ __launch_bounds__(64) void k_fmm_downward(FmmDev f, const int* __restrict__ nodes, int count,
-                                                     const int* __restrict__ parent, int transposed,
-                                                     double* __restrict__ E) {
-  __shared__ TransScratch sc;
-  __shared__ double acc[kPFmm];
-  const int n = nodes[blockIdx.x];
-  const int par = parent[n];
-  if (par < 0) return;
+__global__ __launch_bounds__(64 * kLevelWaves) void k_fmm_downward(FmmDev f, const int* __restrict__ nodes, int count,
+                                                                   const int* __restrict__ parent, int transposed,
+                                                                   int stage, double* __restrict__ E) {
+  extern __shared__ double lvl_tab[];
+  const double* At;
+  const int* Ao;
+  stage_level_table(f, transposed ? 0 : 2, stage, lvl_tab, At, Ao);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TransView sc;
+  double* acc = carve_trans_view(
+      lvl_tab + (stage ? level_table_doubles(f.kernel, f.p, f.nA) : 0) + (size_t)w * trans_view_doubles(f.p), f.p, sc);
   const int P = (f.p + 1) * (f.p + 1);
-  for (int t = threadIdx.x; t < P; t += blockDim.x) { acc[t] = 0.0; sc.b0[t] = E[(long)par * P + t]; }
-  __syncthreads();
-  if (!transposed) translate<false>(f, coef_table(f, 2), 2, par, n, f.p, f.p, 0, sc, acc);
-  else translate<false>(f, coef_table(f, 0), 0, n, par, f.p, f.p, 1, sc, acc);
-  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
+  for (int b = blockIdx.x * kLevelWaves + w; b < count; b += gridDim.x * kLevelWaves) {
+    const int n = nodes[b];
+    const int par = parent[n];
+    if (par < 0) continue;
+    for (int t = lane; t < P; t += 64) { acc[t] = 0.0; sc.b0[t] = E[(long)par * P + t]; }
+    tsync<true>();
+    if (!transposed) translate<true>(f, At, Ao, 2, par, n, f.p, f.p, 0, sc, acc);
+    else translate<true>(f, At, Ao, 0, n, par, f.p, f.p, 1, sc, acc);
+    for (int t = lane; t < P; t += 64) E[(long)n * P + t] += acc[t];
+    tsync<true>();
+  }
 }
 
 // transposed upward pass of one level (adjoint of the downward pass):
 // Lambda[n] += sum_children L2L(n -> child)^T Lambda[child]
-__global__ __launch_bounds__(64) void k_fmm_upward_T(FmmDev f, const int* __restrict__ nodes, int count,
-                                                     const int* __restrict__ child, double* __restrict__ E) {
-  __shared__ TransScratch sc;
-  __shared__ double acc[kPFmm];
-  const int n = nodes[blockIdx.x];
-  if (child[2 * n] < 0) return;
+__global__ __launch_bounds__(64 * kLevelWaves) void k_fmm_upward_T(FmmDev f, const int* __restrict__ nodes, int count,
+                                                                   const int* __restrict__ child, int stage,
+                                                                   double* __restrict__ E) {
+  extern __shared__ double lvl_tab[];
+  const double* At;
+  const int* Ao;
+  stage_level_table(f, 2, stage, lvl_tab, At, Ao);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TransView sc;
+  double* acc = carve_trans_view(
+      lvl_tab + (stage ? level_table_doubles(f.kernel, f.p, f.nA) : 0) + (size_t)w * trans_view_doubles(f.p), f.p, sc);
   const int P = (f.p + 1) * (f.p + 1);
-  for (int t = threadIdx.x; t < P; t += blockDim.x) acc[t] = 0.0;
-  for (int c = 0; c < 2; ++c) {
-    const int ch = child[2 * n + c];
-    __syncthreads();
-    for (int t = threadIdx.x; t < P; t += blockDim.x) sc.b0[t] = E[(long)ch * P + t];
-    __syncthreads();
-    translate<false>(f, coef_table(f, 2), 2, n, ch, f.p, f.p, 1, sc, acc);
+  for (int b = blockIdx.x * kLevelWaves + w; b < count; b += gridDim.x * kLevelWaves) {
+    const int n = nodes[b];
+    if (child[2 * n] < 0) continue;
+    for (int t = lane; t < P; t += 64) acc[t] = 0.0;
+    for (int c = 0; c < 2; ++c) {
+      const int ch = child[2 * n + c];
+      tsync<true>();
+      for (int t = lane; t < P; t += 64) sc.b0[t] = E[(long)ch * P + t];
+      tsync<true>();
+      translate<true>(f, At, Ao, 2, n, ch, f.p, f.p, 1, sc, acc);
+    }
+    for (int t = lane; t < P; t += 64) E[(long)n * P + t] += acc[t];
+    tsync<true>();
   }
-  for (int t = threadIdx.x; t < P; t += blockDim.x) E[(long)n * P + t] += acc[t];
 }
 
 }  // namespace ddlpb
