@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, c
 // Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
 // for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
 template <int LMO>
-__global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
                                                           const int* __restrict__ act_n, const double* __restrict__ xyz,
                                                           const double* __restrict__ rad, const double* __restrict__ leb,
                                                           const int* __restrict__ lptr, const int* __restrict__ lidx,
@@ -313,9 +313,9 @@ __global__ __launch_bounds__(256) void k_sl_adjoint_list(int M, int N, const int
   __shared__ double red[4 * LO];
   const int j = blockIdx.x;
   const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
-  double iu[LMO + 1];
-#pragma unroll
-  for (int l = 0; l <= LMO; ++l) iu[l] = 1.0 / ur[j * LUR + l];
+  // 1 / u_l(r_j) in LDS (registers go to the LO accumulators)
+  __shared__ double iu[LMO + 1];
+  if (threadIdx.x <= LMO) iu[threadIdx.x] = 1.0 / ur[j * LUR + threadIdx.x];
   double acc[LO];
 #pragma unroll
   for (int t = 0; t < LO; ++t) acc[t] = 0.0;
