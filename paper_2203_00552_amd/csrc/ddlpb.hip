@@ -761,8 +761,11 @@ void m2l_config(ddlpb_ctx* c, int kernel, int& nw, bool& alds, size_t& bytes, in
   for (int pass = 0; pass < 2; ++pass) {
     const bool a = pass == 0;
     const void* fn = m2l_fast_fn(NI, kernel, a);
+    hipFuncAttributes fa;
+    HIPCHK(hipFuncGetAttributes(&fa, fn));
     for (int w : {16, 8, 4, 2, 1}) {
       if (c->m2l_waves > 0 && w != c->m2l_waves) continue;
+      if (64 * w > fa.maxThreadsPerBlock) continue;  // beyond the kernel's launch bound
       const size_t b = m2l_fast_lds_bytes(p, nZ, nj, tb.nslot, w, a);
       if (b > (size_t)maxlds) continue;
       if (b > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b));
