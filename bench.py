@@ -66,6 +66,9 @@ def parse():
                    help="precision of the serving requests (the serving workload is specified in mixed precision)")
     p.add_argument("--option", action="append", default=[], metavar="KEY=VALUE",
                    help="extra context option (ddlpb_set_option), repeatable")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="GIB",
+                   help="only copy GIB GiB device to device three times and exit: the calibration run "
+                        "of the HBM traffic counters")
     return p.parse_args()
 
 
@@ -116,6 +119,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_probe > 0:
+        a = torch.ones(args.copy_probe << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_gib": args.copy_probe, "copies": 3}))
+        return
     from paper_2203_00552_amd import Context, inputs
 
     fmm = args.fmm_order if args.fmm_order is not None else 12
