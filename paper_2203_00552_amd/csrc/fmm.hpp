@@ -492,12 +492,12 @@ struct M2LTab {
 // padding has zero values (its src reads stay inside the wavefront's scratch, which
 // holds finite values only).  The trip counts are uniform over the wavefront.
 template <int NI>
-__device__ __forceinline__ void japply_pad(const double* v, const int (&xb)[NI], int shift, int kpack,
+__device__ __forceinline__ void japply_pad(const double* v, const int* xb, int shift, int kpack,
                                            const double* src, double* dst, int lane, int P) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int K = (kpack >> (4 * i)) & 15;
-    const double* x = src + ((xb[i] >> shift) & 0xffff);
+    const double* x = src + ((xb[64 * i] >> shift) & 0xffff);
     double s = 0.0;
     for (int k = 0; k < K; k += 2) {
       s = fma(v[0], x[0], s);
@@ -522,8 +522,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
   double* zl = jv + zt.njpad;
   double* wsb = zl + (ALDS ? zt.nZ : 0);
   int* zs = (int*)(wsb + nw * wd);
+  int* xbl = zs + 2 * zt.nslot;  // [NI][64]: first column of row t of J (low 16 bits) and of J^T (high 16 bits)
   for (int t = threadIdx.x; t < zt.njpad; t += blockDim.x) jv[t] = zt.jpad[t];
   for (int t = threadIdx.x; t < 2 * zt.nslot; t += blockDim.x) zs[t] = zt.slot[t];
+  for (int t = threadIdx.x; t < 64 * NI; t += blockDim.x)
+    xbl[t] = t < P ? ((f.jrow[2 * t + 1] & 4095) | ((f.jrow[2 * (P + t) + 1] & 4095) << 16)) : 0;
   if constexpr (ALDS) {
     for (int t = threadIdx.x; t < zt.nZ; t += blockDim.x) zl[t] = zt.Z[t];
   }
@@ -548,14 +551,12 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
 
   // lane items t = lane + 64 i: degree and order, 6 bits each; first column of the J rows
   int mpack = 0, lpack = 0;
-  int xb[NI];  // first column of the row of J (low 16 bits) and of J^T (high 16 bits)
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int t = lane + 64 * i;
     const int l = (int)sqrtf((float)t + 0.5f);
     mpack |= ((t - l * l - l + 32) & 63) << (6 * i);
     lpack |= (l & 63) << (6 * i);
-    xb[i] = t < P ? ((f.jrow[2 * t + 1] & 4095) | ((f.jrow[2 * (P + t) + 1] & 4095) << 16)) : 0;
   }
 
   for (;;) {
@@ -649,11 +650,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
       }
       if (q + 1 < q1) fetch(lidx[q + 1]);
       tsync<true>();
-      japply_pad<NI>(jv + lane, xb, 0, zt.kpack, b0, b1, lane, P);
+      japply_pad<NI>(jv + lane, xbl + lane, 0, zt.kpack, b0, b1, lane, P);
       tsync<true>();
       zrot_alt<NI>(b1, P, cth, sth, -1.0, lane, mpack);  // pi - theta
       tsync<true>();
-      japply_pad<NI>(jv + nj + lane, xb, 16, zt.kpack, b1, b0, lane, P);
+      japply_pad<NI>(jv + nj + lane, xbl + lane, 16, zt.kpack, b1, b0, lane, P);
       tsync<true>();
       // translation along z
       for (int s = lane; s < zt.nslot; s += 64) {
@@ -686,11 +687,11 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
         if (am) b1[lo * lo + lo - am] = sm;
       }
       tsync<true>();
-      japply_pad<NI>(jv + lane, xb, 0, zt.kpack, b1, b0, lane, P);
+      japply_pad<NI>(jv + lane, xbl + lane, 0, zt.kpack, b1, b0, lane, P);
       tsync<true>();
       zrot_alt<NI>(b0, P, cth, sth, 1.0, lane, mpack);  // theta - pi
       tsync<true>();
-      japply_pad<NI>(jv + nj + lane, xb, 16, zt.kpack, b0, b1, lane, P);
+      japply_pad<NI>(jv + nj + lane, xbl + lane, 16, zt.kpack, b0, b1, lane, P);
       tsync<true>();
       // rotation by phi, scaled by degree, accumulated in registers
 #pragma unroll
@@ -715,7 +716,8 @@ __global__ __launch_bounds__(1024) void k_fmm_m2l_fast(FmmDev f, M2LTab zt, int 
 // LDS bytes of k_fmm_m2l_fast for nw wavefronts per block
 inline size_t m2l_fast_lds_bytes(int p, int nZ, int njpad, int nslot, int nw, bool alds) {
   const size_t d = (size_t)njpad + (alds ? (size_t)nZ : 0) + (size_t)nw * m2l_fast_wave_doubles(p);
-  return d * sizeof(double) + 2 * (size_t)nslot * sizeof(int);
+  const size_t NI = ((size_t)(p + 1) * (p + 1) + 63) / 64;
+  return d * sizeof(double) + (2 * (size_t)nslot + 64 * NI) * sizeof(int);
 }
 
 // downward pass of one level: L[n] += L2L(parent -> n) L[parent]
