@@ -127,7 +127,7 @@ struct ddlpb_ctx {
   int nact = 0;
   long ncap = 0;  // cap pairs (i, n, j) with omega > 0, counted on the host
   double near_pairs_pts = 0.0;  // (active point, listed source sphere) pairs of the near list
-  int nb_dot = 256;
+  int nb_dot = 1024;
   // ---- fast multipole method (fmm_order > 0)
   fmm::Tree tree;
   fmm::Tables tables;
