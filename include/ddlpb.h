@@ -178,7 +178,7 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "leaf_size"      maximal spheres per FMM tree leaf
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
  *   "solver"         0 (default): GMRES as above; 1: the Jacobi-DIIS scheme of
- *                    Sec. 5 (macro-iterations X <- X + L_AB^-1 (g - L X) with DIIS,
+ *                    Sec. 4, opening (macro-iterations X <- X + L_AB^-1 (g - L X) with DIIS,
  *                    L_AB^-1 by DIIS-accelerated Jacobi micro-iterations, both
  *                    stopping on the relative infinity-norm increment, tol and
  *                    tol/100; FP64; stats report the final relative residual)

@@ -32,8 +32,10 @@ LEBEDEV_DEGREE = {6: 3, 14: 5, 26: 7, 38: 9, 50: 11, 74: 13, 86: 15, 110: 17, 14
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle shared library with g++ (FP64, OpenMP)."""
-    cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-shared", "-fPIC", "-o", _LIB, _SRC]
+    tmp = f"{_LIB}.{os.getpid()}.tmp"
+    cmd = ["g++", "-O2", "-fopenmp", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(tmp, _LIB)  # a process that has the old library loaded keeps its copy
     return _LIB
 
 
@@ -132,7 +134,9 @@ class Problem:
     def solve(self, method="auto", tol=1e-12, restart=200, maxit=2000, forces=True):
         """Energy, X, X_adj and forces F = -grad E (e^2/A units).
 
-        method "dense" = LU of the literal matrix; "gmres" = matrix-free GMRES.
+        method "dense" = LU of the literal matrix; "gmres" = matrix-free GMRES;
+        "fgmres" = matrix-free flexible GMRES preconditioned by inner GMRES solves of
+        L_AB (the paper's preconditioner, Sec. 4), for the larger cases.
         """
         if method == "auto":
             method = "dense" if 2 * self.M * self.L <= 4000 else "gmres"
@@ -142,7 +146,8 @@ class Problem:
         F = np.zeros((self.M, 3))
         E = ctypes.c_double(0.0)
         info = np.zeros(2, dtype=np.int32)
-        rc = _load().oracle_solve(*self._args(), ctypes.c_int(0 if method == "dense" else 1),
+        code = {"dense": 0, "gmres": 1, "fgmres": 2}[method]
+        rc = _load().oracle_solve(*self._args(), ctypes.c_int(code),
                                   ctypes.c_double(tol), ctypes.c_int(restart), ctypes.c_int(maxit),
                                   ctypes.byref(E), _ptr(X), _ptr(Xa), _ptr(F) if forces else None,
                                   info.ctypes.data_as(_ip))
@@ -150,6 +155,15 @@ class Problem:
             raise RuntimeError(f"oracle solve failed (rc={rc})")
         return dict(energy=E.value, X=X.reshape(2, self.M, self.L), Xadj=Xa.reshape(2, self.M, self.L),
                     forces=F if forces else None, iters=tuple(int(v) for v in info))
+
+    def single_layer_field(self, m):
+        """Phi[m] at every grid point with chi^eta > 0 (zero elsewhere), [M, N], for
+        per-sphere coefficients m [M, L] (Sec. 2.2, the single-layer potential with
+        basis k_l(kappa |x - x_j|) / k_l(kappa r_j) Y_lm of every sphere j)."""
+        m = np.ascontiguousarray(m, dtype=np.float64).reshape(self.M, self.L)
+        out = np.zeros((self.M, self.N))
+        _load().oracle_single_layer_field(*self._args(), _ptr(m), _ptr(out))
+        return out
 
     def forces_from(self, X, Xadj):
         """Forces from given X and X_adj (Sec. 3 force equation)."""

@@ -736,6 +736,81 @@ int gmres(size_t n, const Op& op, const std::vector<double>& b, std::vector<doub
   return std::sqrt(rn) <= tol * bn * 1.0001 ? 0 : 1;
 }
 
+// Flexible GMRES(m) (right preconditioned, the preconditioned directions stored)
+// with modified Gram-Schmidt; stops when ||b - A x|| <= tol ||b||.  The
+// preconditioner is any approximate inverse, here an inner solve of the sparse
+// part L_AB = [A 0; 0 B], the paper's preconditioner for the coupled system
+// (Sec. 4, opening: L_AB approximates L and is cheap to invert).  It changes the
+// iteration count only; the iterate still satisfies the same residual test.
+template <class Op, class Prec>
+int fgmres(size_t n, const Op& op, const Prec& prec, const std::vector<double>& b, std::vector<double>& x,
+           double tol, int restart, int maxit, int* iters) {
+  double bn = 0;
+  for (double v : b) bn += v * v;
+  bn = std::sqrt(bn);
+  if (bn == 0.0) { std::fill(x.begin(), x.end(), 0.0); if (iters) *iters = 0; return 0; }
+  std::vector<double> r(n), Ax(n);
+  int total = 0;
+  while (total < maxit) {
+    op(x.data(), Ax.data());
+    for (size_t k = 0; k < n; ++k) r[k] = b[k] - Ax[k];
+    double beta = 0;
+    for (double v : r) beta += v * v;
+    beta = std::sqrt(beta);
+    if (beta <= tol * bn) break;
+    std::vector<std::vector<double>> V(1, std::vector<double>(n)), Z;
+    for (size_t k = 0; k < n; ++k) V[0][k] = r[k] / beta;
+    std::vector<std::vector<double>> H(restart + 1, std::vector<double>(restart, 0.0));
+    std::vector<double> cs(restart), sn(restart), gvec(restart + 1, 0.0);
+    gvec[0] = beta;
+    int j = 0;
+    for (; j < restart && total < maxit; ++j, ++total) {
+      Z.emplace_back(n);
+      prec(V[j].data(), Z[j].data());
+      std::vector<double> wv(n);
+      op(Z[j].data(), wv.data());
+      for (int i = 0; i <= j; ++i) {
+        double h = 0;
+        for (size_t k = 0; k < n; ++k) h += wv[k] * V[i][k];
+        H[i][j] = h;
+        for (size_t k = 0; k < n; ++k) wv[k] -= h * V[i][k];
+      }
+      double hn = 0;
+      for (double v : wv) hn += v * v;
+      hn = std::sqrt(hn);
+      H[j + 1][j] = hn;
+      V.emplace_back(n);
+      if (hn > 0) for (size_t k = 0; k < n; ++k) V[j + 1][k] = wv[k] / hn;
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
+        H[i + 1][j] = -sn[i] * H[i][j] + cs[i] * H[i + 1][j];
+        H[i][j] = t;
+      }
+      double den = std::sqrt(H[j][j] * H[j][j] + H[j + 1][j] * H[j + 1][j]);
+      cs[j] = H[j][j] / den;
+      sn[j] = H[j + 1][j] / den;
+      H[j][j] = den;
+      H[j + 1][j] = 0;
+      gvec[j + 1] = -sn[j] * gvec[j];
+      gvec[j] = cs[j] * gvec[j];
+      if (std::fabs(gvec[j + 1]) <= tol * bn) { ++j; ++total; break; }
+    }
+    std::vector<double> yv(j);
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = gvec[i];
+      for (int c = i + 1; c < j; ++c) acc -= H[i][c] * yv[c];
+      yv[i] = acc / H[i][i];
+    }
+    for (int i = 0; i < j; ++i)
+      for (size_t k = 0; k < n; ++k) x[k] += yv[i] * Z[i][k];
+  }
+  op(x.data(), Ax.data());
+  double rn = 0;
+  for (size_t k = 0; k < n; ++k) rn += (b[k] - Ax[k]) * (b[k] - Ax[k]);
+  if (iters) *iters = total;
+  return std::sqrt(rn) <= tol * bn * 1.0001 ? 0 : 1;
+}
+
 // ------------------------------------------------------------------ forces
 // Gradient of the energy via the adjoint method (Sec. 3, force equation):
 // dE = 1/2 < dg - dL X , X_adj >.  With X and X_adj frozen this is the gradient
@@ -973,7 +1048,8 @@ void oracle_dense(ORACLE_ARGS, double* Lout, double* gout) {
 }
 
 // Full energy + adjoint + forces.
-//   method 0: dense LU of the literal matrix;  method 1: GMRES on the matrix-free operator.
+//   method 0: dense LU of the literal matrix;  method 1: GMRES on the matrix-free operator;
+//   method 2: flexible GMRES on it, preconditioned by inner GMRES solves of L_AB.
 //   Outputs (any may be NULL): energy, X [2ML], Xadj [2ML], forces [M][3] (F = -grad E).
 //   info[0..1] = GMRES iterations (primal, adjoint).  Returns 0 on success.
 int oracle_solve(ORACLE_ARGS, int method, double tol, int restart, int maxit, double* energy, double* Xout,
@@ -994,12 +1070,32 @@ int oracle_solve(ORACLE_ARGS, int method, double tol, int restart, int maxit, do
       for (size_t b = 0; b < D; ++b) LT[b * D + a] = Lm[a * D + b];
     Xa = Qv;
     rc |= lu_solve<double>((int)D, LT, Xa);
-  } else {
+  } else if (method == 1) {
     P.rhs(g);
     auto opL = [&](const double* in, double* out) { P.apply(in, out); };
     auto opLT = [&](const double* in, double* out) { P.apply_T(in, out); };
     rc |= gmres(D, opL, g, X, tol, restart, maxit, &it1);
     rc |= 2 * gmres(D, opLT, Qv, Xa, tol, restart, maxit, &it2);
+  } else {
+    // flexible GMRES preconditioned by an inner GMRES solve of L_AB (or L_AB^T) to
+    // relative residual 1e-4 (at most 60 steps), from zero
+    P.rhs(g);
+    auto opL = [&](const double* in, double* out) { P.apply(in, out); };
+    auto opLT = [&](const double* in, double* out) { P.apply_T(in, out); };
+    auto opAB = [&](const double* in, double* out) { P.apply(in, out, 1); };
+    auto opABT = [&](const double* in, double* out) { P.apply_T(in, out, 1); };
+    auto precAB = [&](const double* in, double* out) {
+      std::vector<double> rhs(in, in + D), z(D, 0.0);
+      gmres(D, opAB, rhs, z, 1e-4, 60, 60, nullptr);
+      std::copy(z.begin(), z.end(), out);
+    };
+    auto precABT = [&](const double* in, double* out) {
+      std::vector<double> rhs(in, in + D), z(D, 0.0);
+      gmres(D, opABT, rhs, z, 1e-4, 60, 60, nullptr);
+      std::copy(z.begin(), z.end(), out);
+    };
+    rc |= fgmres(D, opL, precAB, g, X, tol, restart, maxit, &it1);
+    rc |= 2 * fgmres(D, opLT, precABT, Qv, Xa, tol, restart, maxit, &it2);
   }
   double E = 0.0;
   for (int j = 0; j < M; ++j) E += 0.5 * q[j] * X[(size_t)j * L] / std::sqrt(4.0 * PI);
@@ -1013,6 +1109,16 @@ int oracle_solve(ORACLE_ARGS, int method, double tol, int restart, int maxit, do
     for (size_t k = 0; k < grad.size(); ++k) forces_out[k] = -grad[k];
   }
   return rc;
+}
+
+// Single-layer field Phi[m](x_i^n) = sum_j sum_lm m_jlm k_l(kappa|x - x_j|)/k_l(kappa r_j)
+// Y_lm(x - x_j) at the grid points with chi^eta_i > 0 (zero elsewhere), for given
+// per-sphere coefficients m [M][L]; out [M][N].
+void oracle_single_layer_field(ORACLE_ARGS, const double* m, double* Phi) {
+  auto P = make_problem<double>(ORACLE_PASS);
+  std::vector<double> mv(m, m + (size_t)M * P.L), out;
+  P.single_layer_field(mv, out);
+  std::copy(out.begin(), out.end(), Phi);
 }
 
 // Forces for given X and X_adj (e.g. produced elsewhere); forces [M][3] = -grad E.

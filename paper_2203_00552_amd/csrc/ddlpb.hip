@@ -128,6 +128,7 @@ struct ddlpb_ctx {
   long ncap = 0;  // cap pairs (i, n, j) with omega > 0, counted on the host
   double near_pairs_pts = 0.0;  // (active point, listed source sphere) pairs of the near list
   int nb_dot = 1024;
+  int mk = 0;  // vectors the dot-product scratch holds (d_part, d_hv)
   // ---- fast multipole method (fmm_order > 0)
   fmm::Tree tree;
   fmm::Tables tables;
@@ -372,7 +373,10 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_rcn = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
   c->d_rcw = cv.take<double>(std::max<size_t>(c->cap_cap, 1));
   c->d_pidx = cv.take<int>(std::max<size_t>(c->pnz_cap, 1));
-  const int mk = std::max(c->restart, c->inner_iters) + 2;
+  // dot-product scratch: the outer basis, the inner GMRES of either preconditioner and
+  // the DIIS histories all call mdot with at most this many vectors
+  const int mk = std::max(std::max(c->restart, c->inner_iters), std::max(c->pkrylov, c->diis_max)) + 2;
+  c->mk = mk;
   c->d_part = cv.take<double>((size_t)mk * c->nb_dot);
   c->d_hv = cv.take<double>(mk);
   c->d_scal = cv.take<double>(16);
@@ -988,6 +992,7 @@ void precond(ddlpb_ctx* c, bool transpose, const double* v, double* z) {
 // ---- BLAS-1 on the device (deterministic reductions)
 void mdot(ddlpb_ctx* c, int nv, const double* V, long ldv, const double* w, double* h_host) {
   const long D = 2L * c->M * c->L;
+  if (nv < 1 || nv > c->mk) throw HipError{hipErrorInvalidValue};  // scratch holds mk vectors
   hipLaunchKernelGGL(k_mdot_part, dim3(c->nb_dot, nv), dim3(256), 0, c->stream, D, nv, V, ldv, w, c->d_part);
   hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(256), 0, c->stream, c->nb_dot, c->d_part, c->d_hv);
   HIPCHK(hipGetLastError());
@@ -1001,6 +1006,7 @@ double norm2(ddlpb_ctx* c, const double* w) {
 }
 void mupdate(ddlpb_ctx* c, int nv, const double* V, long ldv, const double* h_host, double* w) {
   const long D = 2L * c->M * c->L;
+  if (nv < 1 || nv > c->mk) throw HipError{hipErrorInvalidValue};
   HIPCHK(hipMemcpyAsync(c->d_hv, h_host, nv * sizeof(double), hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_mupdate, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, nv, V, ldv, c->d_hv, w);
   HIPCHK(hipGetLastError());
@@ -1081,6 +1087,7 @@ int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b
       for (int k = i + 1; k < j; ++k) a -= H[(size_t)i * m + k] * y[k];
       y[i] = a / H[(size_t)i * m + i];
     }
+    if (j > c->mk) throw HipError{hipErrorInvalidValue};
     HIPCHK(hipMemcpyAsync(c->d_hv, y.data(), j * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (Z) {
       hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, j, Z, D, c->d_hv, tc);
@@ -1295,6 +1302,7 @@ struct Diis {
       cf[i] = v / G[(size_t)i * A + i];
     }
     const long D = 2L * c->M * c->L;
+    if (n > c->mk) throw HipError{hipErrorInvalidValue};
     HIPCHK(hipMemcpyAsync(c->d_hv, cf.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_mcomb, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, n, F, D, c->d_hv, x);
     HIPCHK(hipGetLastError());
@@ -1302,7 +1310,7 @@ struct Diis {
   }
 };
 
-// The paper's solver (Sec. 5, opening): macro-iterations X <- L_AB^{-1}(g - L_C X)
+// The paper's solver (Sec. 4, opening): macro-iterations X <- L_AB^{-1}(g - L_C X)
 // accelerated by DIIS, L_AB being the preconditioner; each L_AB solve by
 // micro-iterations (Jacobi sweeps X <- b + (I - L_AB) X, the diagonal blocks being
 // the identity, also accelerated by DIIS) started from the previous macro iterate,
@@ -1568,6 +1576,8 @@ void geometry_on_device(ddlpb_ctx* c) {
 int ensure_device(ddlpb_ctx* c) {
   if (c->dev_ready) return DDLPB_OK;
   size_t need = workspace_size(c);
+  // options set after ddlpb_bind_workspace may have enlarged the layout
+  if (c->ws_bound && need > c->ws_bytes) return DDLPB_ENOMEM;
   if (!c->ws_bound) {
     void* p = nullptr;
     if (hipMalloc(&p, need) != hipSuccess) return DDLPB_ENOMEM;
@@ -1819,8 +1829,9 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
   });
 }
 
-int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
-                          double* out) {
+namespace {
+int check_eval_args(const ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
+                    const double* out) {
   if (!c || n_points < 0 || (n_points > 0 && (!points || !out))) return DDLPB_EINVAL;
   if (c->state < 1) return DDLPB_ESTATE;
   for (long k = 0; k < 3L * n_points; ++k)
@@ -1828,39 +1839,55 @@ int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, 
   if (spheres)
     for (int k = 0; k < n_points; ++k)
       if (spheres[k] < 0 || spheres[k] >= c->M) return DDLPB_EINVAL;
-  if (n_points == 0) return DDLPB_OK;
+  return DDLPB_OK;
+}
+// bytes of device staging per evaluation point: the point, its ball and 8 results
+constexpr size_t kEvalBytesPerPoint = 3 * sizeof(double) + 8 * sizeof(double) + sizeof(int);
+// staging layout inside a block of n points: points [n][3], results [n][8], balls [n]
+void eval_staged(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres, double* out,
+                 char* blk) {
+  const size_t bp = 3L * n_points * sizeof(double), bo = 8L * n_points * sizeof(double);
+  double* dp = (double*)blk;
+  double* dout = (double*)(blk + bp);
+  int* dball = (int*)(blk + bp + bo);
+  HIPCHK(hipMemcpyAsync(dp, points, bp, hipMemcpyHostToDevice, c->stream));
+  if (spheres) {
+    HIPCHK(hipMemcpyAsync(dball, spheres, (size_t)n_points * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  } else {
+    hipLaunchKernelGGL(k_nearest_ball, dim3(nblk(n_points, 256)), dim3(256), 0, c->stream, n_points, dp, c->M,
+                       c->d_xyz, c->d_rad, dball);
+    HIPCHK(hipGetLastError());
+  }
+  LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eval_points<LMc>), dim3(nblk(n_points, 256)), dim3(256), 0, c->stream,
+                                          n_points, dp, dball, c->M, c->L, c->LUR, c->d_X, c->d_xyz, c->d_rad,
+                                          c->d_isgr, c->kappa, c->nterms, dout));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, dout, bo, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace
+
+int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
+                          double* out) {
+  int rc = check_eval_args(c, n_points, points, spheres, out);
+  if (rc || n_points == 0) return rc;
   return guarded([&]() -> int {
     // points, balls and results in one temporary device block (freed before return)
-    const size_t bp = 3L * n_points * sizeof(double), bo = 8L * n_points * sizeof(double);
-    const size_t bb = ((size_t)n_points * sizeof(int) + 255) / 256 * 256;
     char* blk = nullptr;
-    if (hipMalloc((void**)&blk, bp + bo + bb) != hipSuccess) { (void)hipGetLastError(); return DDLPB_ENOMEM; }
-    double* dp = (double*)blk;
-    double* dout = (double*)(blk + bp);
-    int* dball = (int*)(blk + bp + bo);
-    int rc = DDLPB_OK;
+    if (hipMalloc((void**)&blk, (size_t)n_points * kEvalBytesPerPoint) != hipSuccess) {
+      (void)hipGetLastError();
+      return DDLPB_ENOMEM;
+    }
     try {
-      HIPCHK(hipMemcpyAsync(dp, points, bp, hipMemcpyHostToDevice, c->stream));
-      if (spheres) {
-        HIPCHK(hipMemcpyAsync(dball, spheres, (size_t)n_points * sizeof(int), hipMemcpyHostToDevice, c->stream));
-      } else {
-        hipLaunchKernelGGL(k_nearest_ball, dim3(nblk(n_points, 256)), dim3(256), 0, c->stream, n_points, dp, c->M,
-                           c->d_xyz, c->d_rad, dball);
-        HIPCHK(hipGetLastError());
-      }
-      LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eval_points<LMc>), dim3(nblk(n_points, 256)), dim3(256), 0,
-                                              c->stream, n_points, dp, dball, c->M, c->L, c->LUR, c->d_X, c->d_xyz,
-                                              c->d_rad, c->d_isgr, c->kappa, c->nterms, dout));
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(out, dout, bo, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
+      eval_staged(c, n_points, points, spheres, out, blk);
     } catch (...) {
       (void)hipStreamSynchronize(c->stream);
       (void)hipFree(blk);
       throw;
     }
     HIPCHK(hipFree(blk));
-    return rc;
+    return DDLPB_OK;
   });
 }
 
@@ -1968,6 +1995,7 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->solver = (int)v;
   } else if (k == "diis_max") {
+    if (fixed) return DDLPB_ESTATE;
     if (!(v >= 2 && v <= 32)) return DDLPB_EINVAL;
     c->diis_max = (int)v;
   } else if (k == "theta") {
@@ -1990,11 +2018,20 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
   for (int i = 0; i < 3 * c->M; ++i)
     if (!std::isfinite(centers[i])) return DDLPB_EINVAL;
   return guarded([&]() -> int {
-    std::vector<double> old = c->x;
-    std::vector<int> onptr = c->nptr, onidx = c->nidx, onrev = c->nrev;
+    // previous geometry, restored when the new one cannot be set up (EGEOM, ENOMEM)
+    const std::vector<double> old = c->x;
+    const std::vector<int> onptr = c->nptr, onidx = c->nidx, onrev = c->nrev, opptr = c->pptr, opidx = c->pidx;
+    const fmm::Tree otree = c->tree;
+    const size_t ocap_est = c->cap_est, onnz = c->nnz_cap, opnz = c->pnz_cap, ocap = c->cap_cap, om2l = c->m2l_cap,
+                 onear = c->near_cap;
+    auto restore = [&]() {
+      c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; c->pptr = opptr; c->pidx = opidx;
+      c->tree = otree; c->cap_est = ocap_est; c->nnz_cap = onnz; c->pnz_cap = opnz; c->cap_cap = ocap;
+      c->m2l_cap = om2l; c->near_cap = onear;
+    };
     c->x.assign(centers, centers + 3L * c->M);
     int rc = build_neighbours(c);
-    if (rc) { c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; return rc; }
+    if (rc) { restore(); return rc; }
     build_pairs(c, c->pdelta, c->pptr, c->pidx);
     if (c->fmm_order > 0) {
       // the leaves sit at the sphere centres: the tree and its lists follow the atoms
@@ -2019,11 +2056,24 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
           c->near_cap = c->tree.near_idx.size() + c->tree.near_idx.size() / 4 + 64;
         }
         size_t need = workspace_size(c);
-        if (c->ws_bound && need > c->ws_bytes) return DDLPB_ENOMEM;
+        if (c->ws_bound && need > c->ws_bytes) {
+          restore();
+          size_t t;
+          carve(c, c->ws, &t);  // device pointers of the previous layout
+          return DDLPB_ENOMEM;
+        }
         if (c->ws_owned && need > c->ws_bytes) {
-          (void)hipFree(c->ws);
+          // the new block first: when it cannot be had, the old one and its state stay
           void* p = nullptr;
-          if (hipMalloc(&p, need) != hipSuccess) { c->ws = nullptr; c->dev_ready = false; return DDLPB_ENOMEM; }
+          if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            restore();
+            size_t t;
+            carve(c, c->ws, &t);
+            return DDLPB_ENOMEM;
+          }
+          HIPCHK(hipStreamSynchronize(c->stream));
+          (void)hipFree(c->ws);
           c->ws = (char*)p;
           c->ws_bytes = need;
         }

@@ -228,4 +228,48 @@ __device__ __forceinline__ R block_sum(R v, R* sh /* >= 16 entries */) {
   return t;
 }
 
+// Compensated FP64 summation (Neumaier): the running sum and, separately, the sum of
+// the rounding errors of every addition (each recovered exactly by TwoSum).
+struct Comp {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return s + c; }
+};
+// a + b for compensated pairs: TwoSum of the sums, the errors added (commutative, so
+// both lanes of a butterfly get the same bits)
+__device__ __forceinline__ Comp comp_merge(const Comp& a, const Comp& b) {
+  Comp r;
+  r.s = a.s + b.s;
+  const double bp = r.s - a.s;
+  r.c = (a.c + b.c) + ((a.s - (r.s - bp)) + (b.s - bp));
+  return r;
+}
+// Deterministic compensated block sum (blockDim.x multiple of 64, <= 1024); the value
+// is valid in all threads.
+__device__ __forceinline__ double block_sum_comp(Comp v, double* sh /* >= 32 entries */) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    Comp o;
+    o.s = __shfl_xor(v.s, off, 64);
+    o.c = __shfl_xor(v.c, off, 64);
+    v = comp_merge(v, o);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) { sh[2 * wid] = v.s; sh[2 * wid + 1] = v.c; }
+  __syncthreads();
+  Comp t;
+  for (int k = 0; k < nw; ++k) {
+    Comp o;
+    o.s = sh[2 * k];
+    o.c = sh[2 * k + 1];
+    t = comp_merge(t, o);
+  }
+  return t.value();
+}
+
 }  // namespace ddlpb

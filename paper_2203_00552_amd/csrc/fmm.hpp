@@ -940,10 +940,10 @@ __global__ __launch_bounds__(256) void k_force_laplace_source_list(int N, const 
                                                                    const int* __restrict__ lptr,
                                                                    const int* __restrict__ lidx,
                                                                    double* __restrict__ out) {
-  __shared__ double sh[16];
+  __shared__ double sh[32];
   const int kq = blockIdx.x;
   const double xk = xyz[3 * kq], yk = xyz[3 * kq + 1], zk = xyz[3 * kq + 2], qk = q[kq];
-  double acc[3] = {0, 0, 0};
+  Comp acc[3];
   for (int t = lptr[kq]; t < lptr[kq + 1]; ++t) {
     const int i = lidx[t];
     if (i == kq) continue;
@@ -958,11 +958,12 @@ __global__ __launch_bounds__(256) void k_force_laplace_source_list(int N, const 
       const double d2 = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2], id = 1.0 / sqrt(d2), id2 = id * id,
                    id3 = id2 * id;
       const double vs = v3[0] * s[0] + v3[1] * s[1] + v3[2] * s[2];
-      for (int a = 0; a < 3; ++a) acc[a] -= qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3));
+      for (int a = 0; a < 3; ++a)
+        acc[a].add(-qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3)));
     }
   }
   for (int c = 0; c < 3; ++c) {
-    double s = block_sum(acc[c], sh);
+    double s = block_sum_comp(acc[c], sh);
     if (threadIdx.x == 0) out[3L * kq + c] += s;
   }
 }

@@ -700,10 +700,10 @@ __global__ void k_mcomb(long D, int nv, const double* __restrict__ V, long ldv, 
 // E = sum_j q_j X_r,j00 / (2 sqrt(4 pi))   (Sec. 3 energy equation, psi_r(x_j) = X_r,j00 Y_00)
 __global__ __launch_bounds__(1024) void k_energy(int M, int L, const double* __restrict__ X, const double* __restrict__ q,
                                                  double* __restrict__ out) {
-  __shared__ double sh[16];
-  double s = 0.0;
-  for (int j = threadIdx.x; j < M; j += blockDim.x) s += q[j] * X[(long)j * L];
-  s = block_sum(s, sh);
+  __shared__ double sh[32];
+  Comp acc;  // compensated: M terms of both signs
+  for (int j = threadIdx.x; j < M; j += blockDim.x) acc.add(q[j] * X[(long)j * L]);
+  const double s = block_sum_comp(acc, sh);
   if (threadIdx.x == 0) out[0] = s * 0.14104739588693907;  // 1/(2 sqrt(4 pi))
 }
 

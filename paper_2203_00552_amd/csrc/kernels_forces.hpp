@@ -182,13 +182,13 @@ __global__ __launch_bounds__(256) void k_force_points(int M, int N, int nact, co
 // sum of the per-point vectors of each sphere (fixed order)
 __global__ __launch_bounds__(256) void k_sum_points(int M, const int* __restrict__ act_ptr, const double* __restrict__ fpt,
                                                     double* __restrict__ out) {
-  __shared__ double sh[16];
+  __shared__ double sh[32];
   const int i = blockIdx.x;
-  double a[3] = {0, 0, 0};
+  Comp a[3];
   for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x)
-    for (int c = 0; c < 3; ++c) a[c] += fpt[3L * k + c];
+    for (int c = 0; c < 3; ++c) a[c].add(fpt[3L * k + c]);
   for (int c = 0; c < 3; ++c) {
-    double s = block_sum(a[c], sh);
+    double s = block_sum_comp(a[c], sh);
     if (threadIdx.x == 0) out[3L * i + c] = s;
   }
 }
@@ -204,10 +204,10 @@ __global__ __launch_bounds__(256) void k_force_laplace_source(int M, int N, int 
                                                               const double* __restrict__ xr,
                                                               const double* __restrict__ etag,
                                                               double* __restrict__ out) {
-  __shared__ double sh[16];
+  __shared__ double sh[32];
   const int kq = blockIdx.x;
   const double xk = xyz[3 * kq], yk = xyz[3 * kq + 1], zk = xyz[3 * kq + 2], qk = q[kq];
-  double acc[3] = {0, 0, 0};
+  Comp acc[3];  // every active point of the other spheres: compensated
   for (int k = threadIdx.x; k < nact; k += blockDim.x) {
     const int i = act_sph[k], n = act_n[k];
     if (i == kq) continue;
@@ -220,10 +220,10 @@ __global__ __launch_bounds__(256) void k_force_laplace_source(int M, int N, int 
     const double d2 = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2], id = 1.0 / sqrt(d2), id2 = id * id, id3 = id2 * id;
     const double vs = v3[0] * s[0] + v3[1] * s[1] + v3[2] * s[2];
     for (int a = 0; a < 3; ++a)
-      acc[a] -= qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3));
+      acc[a].add(-qk * (a1 * (-v3[a] * id3) + a2 * (3.0 * v3[a] * vs * id3 * id2 - s[a] * id3)));
   }
   for (int c = 0; c < 3; ++c) {
-    double s = block_sum(acc[c], sh);
+    double s = block_sum_comp(acc[c], sh);
     if (threadIdx.x == 0) out[3L * kq + c] = s;
   }
 }
@@ -329,12 +329,16 @@ __global__ void k_force_final(int M, const int* __restrict__ nptr, const int* __
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   for (int c = 0; c < 3; ++c) {
-    double g = fself[3L * k + c] + fpts[3L * k + c] + flsrc[3L * k + c] + fysrc[3L * k + c];
+    Comp g;  // compensated per-atom sum of the force terms
+    g.add(fself[3L * k + c]);
+    g.add(fpts[3L * k + c]);
+    g.add(flsrc[3L * k + c]);
+    g.add(fysrc[3L * k + c]);
     for (int b = nptr[k]; b < nptr[k + 1]; ++b) {
       const int i = nidx[b];
-      g -= fnb[3L * (nptr[i] + nrev[b]) + c];
+      g.add(-fnb[3L * (nptr[i] + nrev[b]) + c]);
     }
-    F[3L * k + c] = -g;
+    F[3L * k + c] = -g.value();
   }
 }
 

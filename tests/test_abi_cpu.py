@@ -74,3 +74,26 @@ def test_call_order_and_options():
     assert lib.ddlpb_strerror(-5) == b"solver did not converge"
     lib.ddlpb_free(h)
     lib.ddlpb_free(None)
+
+
+def test_workspace_grows_with_krylov_preconditioner_depth():
+    """The dot-product scratch and the inner basis are sized for the deepest Krylov
+    space (outer restart, inner preconditioner steps or DIIS history), not the
+    restart alone."""
+    lib = _lib.load()
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1.2, 0]])
+    r = np.array([1.5, 1.5, 1.4])
+    q = np.array([0.5, -0.5, 0.0])
+    sizes = {}
+    for k in (16, 32, 64):
+        h = ctypes.c_void_p()
+        assert lib.ddlpb_setup(3, _lib.ptr(x), _lib.ptr(r), _lib.ptr(q), 1.0, 78.54, 0.104, 4, 110, 0,
+                               ctypes.byref(h)) == 0
+        assert lib.ddlpb_set_option(h, b"gmres_restart", 10) == 0
+        assert lib.ddlpb_set_option(h, b"precond_krylov", k) == 0
+        sizes[k] = lib.ddlpb_workspace_bytes(h)
+        lib.ddlpb_free(h)
+    D = 2 * 3 * 25  # 2 M L doubles per vector
+    for a, b in ((16, 32), (32, 64)):
+        # (b - a) more inner basis vectors and (b - a) more rows of 1024 partial dot products
+        assert sizes[b] - sizes[a] >= (b - a) * (D * 8 + 1024 * 8) - 2 * 256

@@ -59,3 +59,30 @@ def test_zero_charges():
     for p in (0, 10):
         E, F, g = _efq(Context(x, r, q, lmax=6, n_lebedev=110, fmm_order=p), 1e-8)
         assert E == 0.0 and np.all(F == 0.0) and np.all(g == 0.0)
+
+
+def test_krylov_preconditioner_deeper_than_restart():
+    """restart 10 with 32 inner GMRES steps on L_AB: the inner Gram-Schmidt uses more
+    vectors than the outer basis; the solve must stay in its workspace and match the
+    oracle."""
+    x, r, q = inputs.small_cluster(4)
+    ctx = Context(x, r, q, lmax=6, n_lebedev=110, options=dict(gmres_restart=10, precond_krylov=32))
+    E, F, _ = _efq(ctx, 1e-11)
+    ref = oracle.Problem(x, r, q, lmax=6, n_lebedev=110).solve("dense")
+    assert abs(E / ref["energy"] - 1) < 1e-8
+    assert _rel(F, ref["forces"]) < 1e-8
+
+
+def test_option_after_bind_is_enomem():
+    """A bound workspace fixes the layout: an option that needs more memory afterwards
+    (precision 2 adds two vectors) makes the next solve fail with ENOMEM instead of
+    writing past the caller's block."""
+    from paper_2203_00552_amd import DDLPBError
+    x, r, q = inputs.small_cluster(0)
+    ctx = Context(x, r, q, lmax=4, n_lebedev=110, torch_workspace=True)
+    before = ctx.workspace_bytes()
+    ctx.set_option("precision", 2)
+    assert ctx.workspace_bytes() > before
+    with pytest.raises(DDLPBError) as e:
+        ctx.solve(1e-8)
+    assert e.value.code == -3

@@ -370,3 +370,113 @@ def test_potentials_regular_at_the_centre():
     pts = np.array([x[i], x[i] + 1e-6 * r[i] * np.array([0.0, 0.6, 0.8])])
     pr, pe, _, _ = P.potentials(ref["X"], pts, spheres=[i, i])
     assert abs(pr[1] - pr[0]) < 1e-5 * abs(pr[0]) and abs(pe[1] - pe[0]) < 1e-5 * abs(pe[0])
+
+
+# --------------------------------------------- global-solution identity (A, B, omega, d)
+def _an(P, vals):
+    """An_i(v)_lm = sum_n w_n Y_lm(s_n) v_n for grid values v [M, N] (pinned tables)."""
+    Y = oracle.sph_harm(P.lmax, P.s)
+    return vals * P.w[None, :] @ Y
+
+
+def _grid_points(P):
+    return P.x[:, None, :] + P.r[:, None, None] * P.s[None, :, :]
+
+
+def _harmonic_poly(rng, deg, pts):
+    """A sum of (c . x)^k with complex null vectors c (c . c = 0): harmonic polynomials of
+    degree <= deg, built without any spherical-harmonic table."""
+    u = np.zeros(pts.shape[:-1])
+    for k in range(deg + 1):
+        a = rng.normal(size=3)
+        b = rng.normal(size=3)
+        b -= a * (a @ b) / (a @ a)
+        b *= np.linalg.norm(a) / np.linalg.norm(b)
+        z = (pts @ a) + 1j * (pts @ b)
+        u += rng.normal() * (z ** k).real / max(1.0, np.abs(z).max()) ** k
+    return u
+
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_global_solution_identity_A(seed):
+    """If u is harmonic of degree <= lmax, X_j = An_j(u on sphere j) reproduces u inside
+    every ball (regular solid harmonics, Sec. 2.2), and sum_j omega_ij = min(f, 1) = 1 - U
+    at every grid point (the d^i factor of Sec. 3.1), so (A X)_i = An_i(U_i u).  Fails for
+    a wrong radial power, a wrong omega or d (including the f > 1 points) or a wrong
+    neighbour list."""
+    x, r, q = inputs.small_cluster(seed)
+    P = oracle.Problem(x, r, q, lmax=6, n_lebedev=110)
+    f, U, _ = P.grid_fields()
+    assert (f > 1.0).sum() > 20  # the d = 1/f branch is exercised
+    rng = np.random.default_rng(11 + seed)
+    pts = _grid_points(P)
+    u = _harmonic_poly(rng, P.lmax, pts - x.mean(0))
+    X = np.zeros((2, P.M, P.L))
+    X[0] = _an(P, u)
+    Y = P.apply(X, part="AB")
+    ref = _an(P, U * u)
+    assert np.abs(Y[0] - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(Y[1]).max() == 0.0
+
+
+@pytest.mark.parametrize("kappa", [0.104, 0.35])
+def test_global_solution_identity_B(kappa):
+    """u = sum_d a_d exp(kappa e_d . x) solves (Laplace - kappa^2) u = 0; its expansion in
+    i_l(kappa |x - x_j|)/i_l(kappa r_j) Y_lm (Sec. 2.2, the B basis) with X_j = An_j(u) is
+    u inside ball j up to the truncation (kappa r)^(lmax+1)/(2 lmax+3)!!, so
+    (B X)_i = An_i(U_i u).  Fails for a wrong kappa in the Bessel ratios, a wrong
+    i_l(kappa r_j) normaliser, omega or d."""
+    x, r, q = inputs.small_cluster(0)
+    P = oracle.Problem(x, r, q, kappa=kappa, lmax=8, n_lebedev=302)
+    f, U, _ = P.grid_fields()
+    assert (f > 1.0).sum() > 20
+    rng = np.random.default_rng(5)
+    pts = _grid_points(P) - x.mean(0)
+    u = np.zeros(pts.shape[:-1])
+    for _ in range(4):
+        e = rng.normal(size=3)
+        u += rng.normal() * np.exp(kappa * pts @ (e / np.linalg.norm(e)))
+    X = np.zeros((2, P.M, P.L))
+    X[1] = _an(P, u)
+    Y = P.apply(X, part="AB")
+    ref = _an(P, U * u)
+    assert np.abs(Y[0]).max() == 0.0
+    assert np.abs(Y[1] - ref).max() < 1e-10 * np.abs(ref).max()
+    # the same data read as the A expansion is wrong at O(kappa^2 r^2): the pin sees kappa
+    X2 = np.zeros_like(X)
+    X2[0] = X[1]
+    assert np.abs(P.apply(X2, part="AB")[0] - ref).max() > 1e3 * np.abs(Y[1] - ref).max()
+
+
+# ----------------------------------------- single layer off the diagonal (addition theorem)
+@pytest.mark.parametrize("kappa", [0.104, 0.6])
+def test_single_layer_addition_theorem(kappa):
+    """exp(-kappa|x - y|)/|x - y| = 8 kappa sum_lm i_l(kappa|y - c|) k_l(kappa|x - c|)
+    Y_lm(y - c) Y_lm(x - c) for |y - c| < |x - c|: with m_jlm = 8 kappa i_l(kappa|y_j - x_j|)
+    k_l(kappa r_j) Y_lm(y_j - x_j) the field Phi[m] of the single-layer basis
+    k_l(kappa|x - x_j|)/k_l(kappa r_j) Y_lm (Sec. 2.2) is the screened potential of unit
+    charges at y_j, at every active grid point of every sphere.  Fails for a wrong
+    k_l normaliser, kappa, harmonic or radial power."""
+    x, r, q = inputs.small_cluster(2)
+    P = oracle.Problem(x, r, q, kappa=kappa, lmax=8, n_lebedev=302)
+    _, U, _ = P.grid_fields()
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=(P.M, 3))
+    d *= (0.05 * r / np.linalg.norm(d, axis=1))[:, None]
+    y = x + d
+    ls = np.arange(P.lmax + 1)
+    deg = np.repeat(ls, 2 * ls + 1)
+    Yd = oracle.sph_harm(P.lmax, d)
+    m = np.zeros((P.M, P.L))
+    for j in range(P.M):
+        il = special.spherical_in(ls, kappa * np.linalg.norm(d[j]))
+        kl = special.spherical_kn(ls, kappa * r[j])
+        m[j] = 8 * kappa * (il * kl)[deg] * Yd[j]
+    Phi = P.single_layer_field(m)
+    pts = _grid_points(P)
+    dist = np.linalg.norm(pts[:, :, None, :] - y[None, None, :, :], axis=-1)
+    ref = (np.exp(-kappa * dist) / dist).sum(-1)
+    act = U > 0
+    assert act.sum() > 500
+    assert np.abs(Phi[~act]).max() == 0.0
+    assert np.abs(Phi[act] - ref[act]).max() < 1e-10 * np.abs(ref[act]).max()
