@@ -134,6 +134,23 @@ int ddlpb_eval_potentials(ddlpb_ctx* ctx, int32_t n_points, const double* points
                           double* out);
 
 /*
+ * ddlpb_eval_potentials_noalloc -- ddlpb_eval_potentials for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid hipMalloc).  Same arguments, results and errors, and the same
+ * kernels; the points, balls and results are staged in a fixed array of the
+ * library's device memory instead of a temporary block, so a call allocates
+ * nothing.  At most DDLPB_NOALLOC_MAX_POINTS points per call (EINVAL beyond).
+ * The array is per GPU (92 bytes per point, 6 MB) and is held from the first call
+ * on a GPU until the process ends; every call on that GPU shares it, so calls that
+ * overlap on one GPU (other threads, other streams) race and must be serialised
+ * by the caller.  No entry needs to start at zero: each call writes every staged
+ * value before reading it.
+ */
+#define DDLPB_NOALLOC_MAX_POINTS 65536
+int ddlpb_eval_potentials_noalloc(ddlpb_ctx* ctx, int32_t n_points, const double* points,
+                                  const int32_t* spheres, double* out);
+
+/*
  * ddlpb_charge_gradient -- dE_s/dq_k for every atom, written to dedq_out [M]
  * (host, e/Angstrom).  The adjoint solution gives the derivative with respect to
  * any parameter of the system at no further solve (Sec. 3, adjoint method):

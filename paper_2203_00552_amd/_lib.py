@@ -18,7 +18,7 @@ EXPORTS = ["ddlpb_setup", "ddlpb_solve", "ddlpb_adjoint", "ddlpb_forces", "ddlpb
            "ddlpb_update_centers", "ddlpb_workspace_bytes", "ddlpb_bind_workspace", "ddlpb_set_stream",
            "ddlpb_get_stats", "ddlpb_strerror", "ddlpb_get_grid", "ddlpb_get_solution", "ddlpb_get_rhs",
            "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset", "ddlpb_charge_gradient",
-           "ddlpb_eval_potentials"]
+           "ddlpb_eval_potentials", "ddlpb_eval_potentials_noalloc"]
 
 
 class DDLPBError(RuntimeError):
@@ -59,6 +59,7 @@ def load():
         lib.ddlpb_forces.argtypes = [c_void_p, _dp]
         lib.ddlpb_charge_gradient.argtypes = [c_void_p, _dp]
         lib.ddlpb_eval_potentials.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
+        lib.ddlpb_eval_potentials_noalloc.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
         lib.ddlpb_free.argtypes = [c_void_p]
         lib.ddlpb_free.restype = None
         lib.ddlpb_set_option.argtypes = [c_void_p, ctypes.c_char_p, c_double]
@@ -158,10 +159,11 @@ class Context:
         check(load().ddlpb_charge_gradient(self._h, ptr(g)), "ddlpb_charge_gradient")
         return g
 
-    def potentials(self, points, spheres=None):
+    def potentials(self, points, spheres=None, noalloc=False):
         """psi_r, psi_e [n] and their gradients [n, 3] at the points [n, 3] from the
         expansions of the given balls (default: the ball with the smallest
-        |x - x_i| / r_i); needs a prior solve."""
+        |x - x_i| / r_i); needs a prior solve.  noalloc: the entry point that stages
+        in the library's fixed device array (at most 65536 points, no allocation)."""
         p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
         n = p.shape[0]
         b = None
@@ -170,9 +172,9 @@ class Context:
             if b.size != n:
                 raise ValueError("one ball index per point")
         out = np.zeros((n, 8))
-        check(load().ddlpb_eval_potentials(self._h, n, ptr(p),
-                                           None if b is None else b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                           ptr(out)), "ddlpb_eval_potentials")
+        fn = load().ddlpb_eval_potentials_noalloc if noalloc else load().ddlpb_eval_potentials
+        check(fn(self._h, n, ptr(p), None if b is None else b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                 ptr(out)), "ddlpb_eval_potentials" + ("_noalloc" if noalloc else ""))
         return out[:, 0].copy(), out[:, 1].copy(), out[:, 2:5].copy(), out[:, 5:8].copy()
 
     def update_centers(self, centers):

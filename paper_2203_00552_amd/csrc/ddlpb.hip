@@ -1866,6 +1866,27 @@ void eval_staged(ddlpb_ctx* c, int32_t n_points, const double* points, const int
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
+// Staging of ddlpb_eval_potentials_noalloc: one fixed array per GPU, held from the
+// first call on that GPU until the process ends.  In host code `scratch` names a
+// host-side stand-in; its device address on each GPU comes from hipGetSymbolAddress
+// (kept per device in g_scratch_dev) and only that address is used.
+constexpr size_t kNoallocMaxPoints = DDLPB_NOALLOC_MAX_POINTS;
+constexpr size_t kScratchBytes = kNoallocMaxPoints * kEvalBytesPerPoint;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_dev;
+char* scratch_on_current_device() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_dev.find(dev);
+  if (it != g_scratch_dev.end()) return it->second;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p || ((uintptr_t)p & 255) != 0) throw HipError{hipErrorInvalidSymbol};
+  g_scratch_dev[dev] = (char*)p;
+  return (char*)p;
+}
 }  // namespace
 
 int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
@@ -1887,6 +1908,20 @@ int ddlpb_eval_potentials(ddlpb_ctx* c, int32_t n_points, const double* points, 
       throw;
     }
     HIPCHK(hipFree(blk));
+    return DDLPB_OK;
+  });
+}
+
+int ddlpb_eval_potentials_noalloc(ddlpb_ctx* c, int32_t n_points, const double* points, const int32_t* spheres,
+                                  double* out) {
+  int rc = check_eval_args(c, n_points, points, spheres, out);
+  if (rc) return rc;
+  if ((size_t)n_points > kNoallocMaxPoints) return DDLPB_EINVAL;
+  if (n_points == 0) return DDLPB_OK;
+  return guarded([&]() -> int {
+    // every staged entry is written before it is read (copies, ball search, kernel):
+    // nothing of the previous call's contents is used
+    eval_staged(c, n_points, points, spheres, out, scratch_on_current_device());
     return DDLPB_OK;
   });
 }
