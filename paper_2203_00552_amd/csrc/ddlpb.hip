@@ -24,6 +24,7 @@
 #include "kernels_forces.hpp"
 #include "fmm.hpp"
 #include "fmm_host.hpp"
+#include "fmm_lane_api.hpp"
 
 using namespace ddlpb;
 
@@ -90,6 +91,7 @@ struct ddlpb_ctx {
   bool warm_start = true;
   double theta = 0.6;
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic, -1: block kernel)
+  int m2l_lane = 1;           // order 12: the one-translation-per-lane M2L kernels (when m2l_waves is 0)
   int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
   struct M2LCfg { bool valid = false, alds = false; int nw = 0, per_cu = 0; size_t bytes = 0; } m2l_cfg[2];
   // ---- host analysis
@@ -795,12 +797,76 @@ void launch_m2l_fast(ddlpb_ctx* c, const FmmDev& f, const M2LTab& zt, int nw, bo
 __global__ void k_zero_ints(int* p, int n) {
   for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
+
+// Tables of the order-12 lane kernels, per device: J and J^T in the pattern order of
+// fmm_lane_api.hpp, uploaded once into each instance's constant arrays after checking
+// that every nonzero of the numerical J lies inside the pattern.  State per device:
+// 1 ready, -1 unusable (pattern mismatch).
+std::mutex g_lane_mu;
+std::map<int, int> g_lane_state;
+int lane_tables_ready(const fmm::Tables& tb) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  auto it = g_lane_state.find(dev);
+  if (it != g_lane_state.end()) return it->second;
+  int state = 1;
+  if (tb.pmax != lane12::kP) state = -1;
+  std::vector<double> J, JT;
+  for (int l = 0; state > 0 && l <= lane12::kP; ++l) {
+    const int w = 2 * l + 1;
+    auto val = [&](int a, int b) { return tb.J[tb.Joff[l] + a * w + b]; };
+    for (int a = 0; a < w; ++a)
+      for (int b = 0; b < w; ++b) {
+        if (lane12::pat(false, l, a, b)) J.push_back(val(a, b));
+        else if (val(a, b) != 0.0) state = -1;
+        if (lane12::pat(true, l, a, b)) JT.push_back(val(b, a));
+      }
+  }
+  if (state > 0 && ((int)J.size() != lane12::kJn || (int)JT.size() != lane12::kJTn)) state = -1;
+  if (state > 0) {
+    HIPCHK(lane12::upload_yf(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yt(J.data(), JT.data()));
+    HIPCHK(lane12::upload_lf(J.data(), JT.data()));
+    HIPCHK(lane12::upload_lt(J.data(), JT.data()));
+  }
+  g_lane_state[dev] = state;
+  return state;
+}
+// launch of the lane kernel of the pass; false when it does not apply
+bool launch_m2l_lane(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx, int transposed, const double* in,
+                     double* out) {
+  if (f.p != lane12::kP || !c->m2l_lane || c->m2l_waves != 0) return false;
+  if (lane_tables_ready(c->tables) < 0) return false;
+  const int which = (f.kernel == 0 ? 0 : 2) + (transposed ? 1 : 0);
+  int per_cu = 0, dev = 0, ncu = 0;
+  hipError_t (*occ[4])(int*) = {lane12::occupancy_yf, lane12::occupancy_yt, lane12::occupancy_lf,
+                                lane12::occupancy_lt};
+  HIPCHK(occ[which](&per_cu));
+  if (per_cu < 1) return false;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int groups = (c->tree.nnodes + 64 / lane12::kGroup - 1) / (64 / lane12::kGroup);
+  const int blocks = std::max(1, std::min(ncu * per_cu, (groups + lane12::kLaneWaves - 1) / lane12::kLaneWaves));
+  lane12::LaneTab t;
+  t.Z = c->d_fZ[f.kernel][transposed ? 1 : 0];
+  t.order = c->d_fm2lord;
+  t.counter = c->d_fctr;
+  c->m2l_layout = 100 + which;
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 1);
+  HIPCHK(hipGetLastError());
+  hipError_t (*fn[4])(const FmmDev&, const lane12::LaneTab&, int, const int*, const int*, const double*, double*, int,
+                      hipStream_t) = {lane12::launch_yf, lane12::launch_yt, lane12::launch_lf, lane12::launch_lt};
+  HIPCHK(fn[which](f, t, c->tree.nnodes, lptr, lidx, in, out, blocks, c->stream));
+  return true;
+}
 void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx, int transposed, const double* in,
                 double* out) {
   const auto& t = c->tree;
   const auto& tb = c->tables;
   KScope ks(c, f.kernel == 0 ? (transposed ? "m2l_yukawa_T" : "m2l_yukawa") : (transposed ? "m2l_laplace_T" : "m2l_laplace"),
             flops_m2l_fast(f.kernel, f.p, tb.Jval.size()) * (double)t.m2l_src.size());
+  if (launch_m2l_lane(c, f, lptr, lidx, transposed, in, out)) return;
   int nw, per_cu;
   bool alds;
   size_t bytes;
@@ -2026,6 +2092,9 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (!(v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
     c->m2l_cfg[0].valid = c->m2l_cfg[1].valid = false;
+  } else if (k == "m2l_lane") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->m2l_lane = (int)v;
   } else if (k == "solver") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->solver = (int)v;

@@ -15,32 +15,13 @@
 // vectors in LDS.
 #pragma once
 #include "device_math.hpp"
+#include "fmm_types.hpp"
 
 namespace ddlpb {
 
 constexpr int kPmaxFmm = 20;
 constexpr int kPFmm = (kPmaxFmm + 1) * (kPmaxFmm + 1);
 
-struct FmmDev {
-  int kernel;            // 0 Yukawa, 1 Laplace
-  int p;                 // expansion order of the tree
-  double kappa;
-  const double* A;       // packed Yukawa coefficients (see Aoff)
-  const int* Aoff;       // offsets [P1][P1][P1]
-  int nA;                // entries of A
-  const double* AL;      // Laplace coefficients [3][P1][P1][P1]
-  const double* J;       // packed J_l blocks
-  const int* Joff;
-  const double* jval;    // sparse rows of J and J^T (values)
-  const int* jrow;       // [2][L][2]: offset, first column | count << 12 | step << 20
-  int njval;
-  const double* center;  // [nn][3]
-  const double* radius;  // [nn]
-  const double* kR;      // [nn][P1]: k_l(kappa R_node)
-  const double* kRi;     // [nn][P1]: 1 / k_l(kappa R_node)
-  const double* iR;      // [nn][P1]: i_l(kappa R_node)
-  double kinv;           // 1 / kappa
-};
 
 // The same scratch as pointers into dynamic LDS, sized for the tree's order p
 struct TransView {

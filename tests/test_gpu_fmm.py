@@ -170,3 +170,26 @@ def test_fmm_charge_gradient():
     f.adjoint(1e-10)
     g = f.charge_gradient()
     assert abs((q * g).sum() / (2 * E) - 1) < 1e-7
+
+
+@pytest.mark.parametrize("n,lmax", [(300, 8), (1500, 6)])
+def test_m2l_lane_kernel_agrees(n, lmax):
+    """Order 12: the one-translation-per-lane multipole-to-local kernels (screened
+    Coulomb in the operator and its transpose, Coulomb in the right-hand side and the
+    forces) give the operator, its transpose, the energy and the forces of the
+    wavefront kernel to rounding."""
+    x, r, q = inputs.lattice_cluster(n, seed=7)
+    L = (lmax + 1) ** 2
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(2, n, L))
+    res = []
+    for lane in (1, 0):
+        f = Context(x, r, q, lmax=lmax, n_lebedev=302, fmm_order=12, options={"m2l_lane": lane})
+        Y, YT = f.apply(X), f.apply(X, transpose=True)
+        E = f.solve(1e-10)
+        f.adjoint(1e-10)
+        res.append((Y, YT, E, f.forces()))
+    (Y1, YT1, E1, F1), (Y0, YT0, E0, F0) = res
+    assert _rel(Y1, Y0) < 1e-12 and _rel(YT1, YT0) < 1e-12
+    assert abs(E1 / E0 - 1) < 1e-10
+    assert _rel(F1, F0) < 1e-8
