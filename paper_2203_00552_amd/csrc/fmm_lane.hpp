@@ -93,20 +93,13 @@ __device__ __forceinline__ void rs_step(const double (&in)[N], double (&out)[(N 
   });
 }
 
-// cos(m a), sin(m a) for m = 0..p of the two rotation angles, by the recurrence of
-// (cos a + i sin a)^m
-__device__ __forceinline__ void trig_tables(double c1, double s1, double ct, double st, double (&cph)[kP1],
-                                            double (&sph)[kP1], double (&cth)[kP1], double (&sth)[kP1]) {
-  cph[0] = 1.0; sph[0] = 0.0; cth[0] = 1.0; sth[0] = 0.0;
-  sfor<kP>([&](auto M_) {
-    constexpr int m = decltype(M_)::value + 1;
-    cph[m] = cph[m - 1] * c1 - sph[m - 1] * s1;
-    sph[m] = sph[m - 1] * c1 + cph[m - 1] * s1;
-    cth[m] = cth[m - 1] * ct - sth[m - 1] * st;
-    sth[m] = sth[m - 1] * ct + cth[m - 1] * st;
-  });
+// (c, s) <- (c, s) * (c1, s1): the next power of the unit complex number c1 + i s1
+// (cos and sin of the next multiple of the angle)
+__device__ __forceinline__ void cmul_step(double& c, double& s, double c1, double s1) {
+  const double t = c * c1 - s * s1;
+  s = s * c1 + c * s1;
+  c = t;
 }
-
 
 // the pattern entries of row a of J (TRJ false) or J^T (TRJ true), degree l, into r
 // (loaded after dep is known)
@@ -150,16 +143,40 @@ __device__ __forceinline__ void japply(const double (&b)[2 * l + 1], double (&c)
   });
 }
 
-// the coefficients of one (lo, li, |m|) entry of the z translation from the table in
-// LDS into r (loaded after dep is known)
-template <bool YUK, int lo, int am, int li>
-__device__ __forceinline__ void zrow_load(ldbl* zs, double (&r)[kZMax], double dep) {
-  if constexpr (lo <= kP && li <= kP) {
-    constexpr int off = zoff(YUK, lo, am, li), cnt = YUK ? nks(lo, li, am) : 1;
+// The z translation of order |m| = am walks its coefficients as a flat sequence of
+// terms (lo, li, k): output degree lo, input degree li and, for the screened Coulomb
+// kernel, the k-th coefficient of the sum against k_n(z) z^n (n of them for the
+// pair).  The table holds each (lo, am) row contiguously.
+struct ZTerm {
+  int lo, li, k, n, off;
+};
+constexpr int zterm_count(bool yuk, int am) {
+  int c = 0;
+  for (int lo = am; lo <= kP; ++lo)
+    for (int li = am; li <= kP; ++li) c += yuk ? nks(lo, li, am) : 1;
+  return c;
+}
+constexpr ZTerm zterm(bool yuk, int am, int t) {
+  for (int lo = am; lo <= kP; ++lo)
+    for (int li = am; li <= kP; ++li) {
+      const int n = yuk ? nks(lo, li, am) : 1;
+      if (t < n) return ZTerm{lo, li, t, n, zoff(yuk, lo, am, li) + t};
+      t -= n;
+    }
+  return ZTerm{-1, -1, -1, 0, 0};
+}
+constexpr int kZChunk = 4;  // coefficients fetched per step, one step ahead
+
+// the coefficients of chunk c of the terms of order am, from the table in LDS, into r
+// (loaded after dep is known)
+template <bool YUK, int am, int c>
+__device__ __forceinline__ void zchunk_load(ldbl* zs, double (&r)[kZChunk], double dep) {
+  constexpr int nt = zterm_count(YUK, am);
+  if constexpr (c * kZChunk < nt) {
     ldbl* p = pin(zs, dep);
-    sfor<cnt>([&](auto I_) {
-      constexpr int i = decltype(I_)::value;
-      r[i] = p[off + i];
+    sfor<kZChunk>([&](auto I_) {
+      constexpr int t = c * kZChunk + decltype(I_)::value;
+      if constexpr (t < nt) r[decltype(I_)::value] = p[zterm(YUK, am, t).off];
     });
   }
 }
@@ -173,6 +190,7 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
                                                                 const double* __restrict__ Ein,
                                                                 double* __restrict__ Eout) {
   __shared__ double zsm[kZYn];
+  __shared__ double accs[kOwn][64 * kLaneWaves];  // each lane's 11 running sums (own column)
   for (int i = threadIdx.x; i < (YUK ? kZYn : kZLn); i += blockDim.x) zsm[i] = t.Z[i];
   __syncthreads();  // the only barrier: afterwards every wavefront takes work on its own
   ldbl* zl = (ldbl*)zsm;
@@ -194,9 +212,8 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
     mx = __builtin_amdgcn_readfirstlane(mx);
     const int nf = n >= 0 ? n : 0;
     const double cnx = f.center[3 * nf], cny = f.center[3 * nf + 1], cnz = f.center[3 * nf + 2];
-    double acc[kOwn];
 #pragma unroll
-    for (int i = 0; i < kOwn; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kOwn; ++i) accs[i][threadIdx.x] = 0.0;
     for (int c = 0; c < mx; c += kGroup) {
       const int q = q0 + c + j;
       const bool act = q < q1;
@@ -218,47 +235,29 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
         s1 = dy * ir;
       }
       const double ct = dz * irho, st = rxy * irho;
-      // cos / sin of m phi and m theta (recomputed for the second rotation so that the
-      // tables are not held across the z translation)
-      double cph[kP1], sph[kP1], cth[kP1], sth[kP1];
-      trig_tables(c1, s1, ct, st, cph, sph, cth, sth);
-      // degree scales of the input (list member o) and of the output (fixed node n)
-      double sin_[kP1], sout[kP1];
+      // cos / sin of m phi and m theta come from the recurrence of (cos a + i sin a)^m,
+      // run again inside every degree (holding the tables would cost 104 registers)
+      // degree scales of the input (the list member o): screened Coulomb forward
+      // 1/k_l(kappa R_o) (-1)^l, transposed i_l(kappa R_o), times (kappa rho)^-l;
+      // Coulomb forward (R_o/rho)^(l+1), transposed (R_o/rho)^l
+      double sin_[kP1];
       if constexpr (YUK) {
         const double zi = irho * f.kinv;
         double zl = 1.0;
         sfor<kP1>([&](auto L_) {
           constexpr int l = decltype(L_)::value;
           const double sg = (l & 1) ? -1.0 : 1.0;
-          // forward: source o (1/k_l(kappa R_o), (-1)^l), target n (i_l(kappa R_n));
-          // transposed: the roles of the two scales are exchanged
           const double ri = TR ? f.iR[o * kP1 + l] : sg * f.kRi[o * kP1 + l];
-          const double ro = TR ? sg * f.kRi[nf * kP1 + l] : f.iR[nf * kP1 + l];
           sin_[l] = act ? ri * zl : 0.0;
-          sout[l] = ro * zl;
           zl *= zi;
         });
       } else {
-        const double Ro = f.radius[o] * irho, Rn = f.radius[nf] * irho;
-        // forward: (R_S/rho)^(l+1) in, (R_T/rho)^l out; transposed: (R_T/rho)^l in, (R_S/rho)^(l+1) out
-        double pi = TR ? 1.0 : Ro, po = TR ? Rn : 1.0;
+        const double Ro = f.radius[o] * irho;
+        double pi = TR ? 1.0 : Ro;
         sfor<kP1>([&](auto L_) {
           constexpr int l = decltype(L_)::value;
           sin_[l] = act ? pi : 0.0;
-          sout[l] = po;
           pi *= Ro;
-          po *= Rn;
-        });
-      }
-      // k_n(z) z^n, n = 0..2p, by the upward recurrence kt_{n+1} = z^2 kt_{n-1} + (2n+1) kt_n
-      double kt[2 * kP + 1];
-      if constexpr (YUK) {
-        const double z = f.kappa * rho, z2 = z * z;
-        kt[0] = 1.5707963267948966 * exp(-z) * irho * f.kinv;
-        kt[1] = kt[0] * (z + 1.0);
-        sfor<2 * kP - 1>([&](auto N_) {
-          constexpr int nn1 = decltype(N_)::value + 1;
-          kt[nn1 + 1] = z2 * kt[nn1 - 1] + (2.0 * nn1 + 1.0) * kt[nn1];
         });
       }
       // the list member's expansion
@@ -274,17 +273,22 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
         constexpr int l = decltype(L_)::value, w = 2 * l + 1;
         double b[w], cc[w];
         b[l] = v[l * l + l] * sin_[l];
+        double cm = 1.0, sm = 0.0;
         sfor<l>([&](auto M_) {
           constexpr int m = decltype(M_)::value + 1;
+          cmul_step(cm, sm, c1, s1);
           const double a = v[l * l + l + m], bb = v[l * l + l - m];
-          b[l + m] = (a * cph[m] + bb * sph[m]) * sin_[l];
-          b[l - m] = (bb * cph[m] - a * sph[m]) * sin_[l];
+          b[l + m] = (a * cm + bb * sm) * sin_[l];
+          b[l - m] = (bb * cm - a * sm) * sin_[l];
         });
         japply<l, false>(b, cc);
+        cm = 1.0;
+        sm = 0.0;
         sfor<l>([&](auto M_) {
           constexpr int m = decltype(M_)::value + 1;
+          cmul_step(cm, sm, ct, st);
           const double sg = (m & 1) ? -1.0 : 1.0;
-          const double co = sg * cth[m], si = -sg * sth[m];
+          const double co = sg * cm, si = -sg * sm;
           const double a = cc[l + m], bb = cc[l - m];
           cc[l + m] = a * co - bb * si;
           cc[l - m] = a * si + bb * co;
@@ -293,35 +297,47 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
 #pragma unroll
         for (int a = 0; a < w; ++a) v[l * l + a] = b[a];
       });
+      // k_n(z) z^n, n = 0..2p, by the upward recurrence kt_{n+1} = z^2 kt_{n-1} + (2n+1) kt_n
+      double kt[2 * kP + 1];
+      if constexpr (YUK) {
+        double rz = rho;
+        asm volatile("" : "+v"(rz) : "v"(v[0]));  // computed here, after the first rotation
+        const double z = f.kappa * rz, z2 = z * z;
+        kt[0] = 1.5707963267948966 * exp(-z) / z;
+        kt[1] = kt[0] * (z + 1.0);
+        sfor<2 * kP - 1>([&](auto N_) {
+          constexpr int nn1 = decltype(N_)::value + 1;
+          kt[nn1 + 1] = z2 * kt[nn1 - 1] + (2.0 * nn1 + 1.0) * kt[nn1];
+        });
+      }
       // translation along z, per order |m| (the same matrix for +m and -m); the
-      // coefficients of the next (lo, li) entry are fetched while one is applied
+      // coefficients are fetched a chunk ahead
       sfor<kP1>([&](auto AM_) {
-        constexpr int am = decltype(AM_)::value, nb = kP1 - am;
+        constexpr int am = decltype(AM_)::value, nb = kP1 - am, nt = zterm_count(YUK, am);
         double op[nb], om[nb];
 #pragma unroll
         for (int x = 0; x < nb; ++x) { op[x] = 0.0; om[x] = 0.0; }
-        double zc[kZMax], zn[kZMax];
-        double dep = v[am * am + am];
-        zrow_load<YUK, am, am, am>(zl, zc, dep);
-        sfor<nb * nb>([&](auto G_) {
-          constexpr int g = decltype(G_)::value, lo = am + g / nb, li = am + g % nb;
-          constexpr int g2 = g + 1, lo2 = am + g2 / nb, li2 = am + g2 % nb;
-          if constexpr (g2 < nb * nb) zrow_load<YUK, lo2, am, li2>(zl, zn, dep);
-          double e;
+        double cur[kZChunk], nxt[kZChunk];
+        double dep = v[am * am + am], e = 0.0;
+        zchunk_load<YUK, am, 0>(zl, cur, dep);
+        sfor<nt>([&](auto T_) {
+          constexpr int t = decltype(T_)::value, pos = t % kZChunk;
+          constexpr ZTerm z = zterm(YUK, am, t);
+          if constexpr (pos == 0) zchunk_load<YUK, am, t / kZChunk + 1>(zl, nxt, dep);
           if constexpr (YUK) {
-            e = 0.0;
-            sfor<nks(lo, li, am)>([&](auto K_) {
-              constexpr int q2 = decltype(K_)::value;
-              e = fma(zc[q2], kt[lo + li - am - q2], e);
-            });
+            e = z.k == 0 ? cur[pos] * kt[z.lo + z.li - am] : fma(cur[pos], kt[z.lo + z.li - am - z.k], e);
           } else {
-            e = zc[0];
+            e = cur[pos];
           }
-          op[lo - am] = fma(e, v[li * li + li + am], op[lo - am]);
-          if constexpr (am > 0) om[lo - am] = fma(e, v[li * li + li - am], om[lo - am]);
-          dep = e;
+          if constexpr (z.k == z.n - 1) {
+            op[z.lo - am] = fma(e, v[z.li * z.li + z.li + am], op[z.lo - am]);
+            if constexpr (am > 0) om[z.lo - am] = fma(e, v[z.li * z.li + z.li - am], om[z.lo - am]);
+            dep = e;
+          }
+          if constexpr (pos == kZChunk - 1) {
 #pragma unroll
-          for (int x = 0; x < kZMax; ++x) zc[x] = zn[x];
+            for (int x = 0; x < kZChunk; ++x) cur[x] = nxt[x];
+          }
         });
         sfor<nb>([&](auto LO_) {
           constexpr int lo = am + decltype(LO_)::value;
@@ -329,34 +345,62 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
           if constexpr (am > 0) v[lo * lo + lo - am] = om[lo - am];
         });
       });
+      // degree scales of the output (the fixed node n): screened Coulomb forward
+      // i_l(kappa R_n), transposed 1/k_l(kappa R_n) (-1)^l, times (kappa rho)^-l;
+      // Coulomb forward (R_n/rho)^l, transposed (R_n/rho)^(l+1); read after the
+      // translation so that they are not held across it
+      double sout[kP1];
+      {
+        int nfp = nf;
+        double irp = irho;
+        asm volatile("" : "+v"(nfp), "+v"(irp) : "v"(v[0]));
+        if constexpr (YUK) {
+          const double zi = irp * f.kinv;
+          double zl = 1.0;
+          sfor<kP1>([&](auto L_) {
+            constexpr int l = decltype(L_)::value;
+            const double sg = (l & 1) ? -1.0 : 1.0;
+            sout[l] = (TR ? sg * f.kRi[nfp * kP1 + l] : f.iR[nfp * kP1 + l]) * zl;
+            zl *= zi;
+          });
+        } else {
+          const double Rn = f.radius[nfp] * irp;
+          double po = TR ? Rn : 1.0;
+          sfor<kP1>([&](auto L_) {
+            constexpr int l = decltype(L_)::value;
+            sout[l] = po;
+            po *= Rn;
+          });
+        }
+      }
       // back to the original frame: J, z-rotation by theta - pi, J^T, z-rotation by
       // phi with the output scale
-      {
-        double c1b = c1, s1b = s1, ctb = ct, stb = st;
-        asm volatile("" : "+v"(c1b), "+v"(s1b), "+v"(ctb), "+v"(stb));  // a fresh evaluation, not a reuse
-        trig_tables(c1b, s1b, ctb, stb, cph, sph, cth, sth);
-      }
       sfor<kP1>([&](auto L_) {
         constexpr int l = decltype(L_)::value, w = 2 * l + 1;
         double b[w], cc[w];
 #pragma unroll
         for (int a = 0; a < w; ++a) b[a] = v[l * l + a];
         japply<l, false>(b, cc);
+        double cm = 1.0, sm = 0.0;
         sfor<l>([&](auto M_) {
           constexpr int m = decltype(M_)::value + 1;
+          cmul_step(cm, sm, ct, st);
           const double sg = (m & 1) ? -1.0 : 1.0;
-          const double co = sg * cth[m], si = sg * sth[m];
+          const double co = sg * cm, si = sg * sm;
           const double a = cc[l + m], bb = cc[l - m];
           cc[l + m] = a * co - bb * si;
           cc[l - m] = a * si + bb * co;
         });
         japply<l, true>(cc, b);
         v[l * l + l] = b[l] * sout[l];
+        cm = 1.0;
+        sm = 0.0;
         sfor<l>([&](auto M_) {
           constexpr int m = decltype(M_)::value + 1;
+          cmul_step(cm, sm, c1, s1);
           const double a = b[l + m], bm = b[l - m];
-          v[l * l + l + m] = (a * cph[m] - bm * sph[m]) * sout[l];
-          v[l * l + l - m] = (a * sph[m] + bm * cph[m]) * sout[l];
+          v[l * l + l + m] = (a * cm - bm * sm) * sout[l];
+          v[l * l + l - m] = (a * sm + bm * cm) * sout[l];
         });
       });
       // sum of the group's 16 vectors, scattered: afterwards this lane holds the sums of
@@ -367,13 +411,13 @@ __global__ __launch_bounds__(64 * kLaneWaves) void k_fmm_m2l_lane(FmmDev f, Lane
       rs_step<43, 0x4E>(r2, r3, b1);    // quad permutation (2, 3, 0, 1)
       rs_step<22, 0xB1>(r3, r4, b0);    // quad permutation (1, 0, 3, 2)
 #pragma unroll
-      for (int i = 0; i < kOwn; ++i) acc[i] += r4[i];
+      for (int i = 0; i < kOwn; ++i) accs[i][threadIdx.x] += r4[i];
     }
     if (n >= 0) {
 #pragma unroll
       for (int i = 0; i < kOwn; ++i) {
         const int k = kGroup * i + jr;
-        if (k < kPP) Eout[(long)n * kPP + k] = acc[i];
+        if (k < kPP) Eout[(long)n * kPP + k] = accs[i][threadIdx.x];
       }
     }
   }
