@@ -75,7 +75,9 @@ typedef struct {
  *   eps_in, eps_out > 0; kappa > 0 (1/Angstrom)
  *   lmax        0..10, maximal harmonic degree on every sphere (Sec. 2.2)
  *   n_lebedev   one of 6, 14, 26, 38, 50, 74, 86, 110, 146, 170, 194, 230, 266, 302,
- *               350, 434, 590, 770, 974 and of quadrature degree >= 2*lmax
+ *               350, 434, 590, 770, 974 and of quadrature degree >= 2*lmax + 2 (the
+ *               projection through the switching function needs the margin: lmax 8
+ *               on 110 points, degree 17, is rejected)
  *   fmm_order   0 = direct O(M^2) single layer and vacuum field;
  *               p = lmax+1..16: fast multipole method of order p (Appendix) for
  *               the single layer (screened Coulomb) and the vacuum (Coulomb)
@@ -161,6 +163,18 @@ int ddlpb_eval_potentials_noalloc(ddlpb_ctx* ctx, int32_t n_points, const double
  */
 int ddlpb_charge_gradient(ddlpb_ctx* ctx, double* dedq_out);
 
+/*
+ * ddlpb_dielectric_gradient -- dE_s/d eps_in and dE_s/d eps_out, written to
+ * dedeps_out [2] (host, e^2/Angstrom per unit of permittivity), from the same adjoint
+ * solution (Sec. 3: dE/d lambda = 1/2 <X_adj, dg/d lambda - (dL/d lambda) X> for any
+ * parameter lambda).  The permittivities enter the right-hand side through psi_0
+ * (~ 1/eps_in) and the normal-derivative term (~ 1/eps_out), and the operator only
+ * through eps_in/eps_out in C1, so one extra single-layer product (C1 X_r) and three
+ * dot products suffice; eps_in dE/d eps_in + eps_out dE/d eps_out = -E.
+ * Requires a prior ddlpb_adjoint (else ESTATE).  Errors: EINVAL, ESTATE, EDEVICE.
+ */
+int ddlpb_dielectric_gradient(ddlpb_ctx* ctx, double* dedeps_out);
+
 /* ddlpb_free -- release the context and any device memory it allocated. NULL is a no-op. */
 void ddlpb_free(ddlpb_ctx* ctx);
 
@@ -192,7 +206,6 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    r_i + r_j + delta (Angstrom); < 0 (default) disables it
  *   "inner_iters"    inner GMRES steps on P per outer step (1..200, default 12)
  *   "max_iter"       maximal GMRES iterations per solve
- *   "leaf_size"      maximal spheres per FMM tree leaf
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
  *   "solver"         0 (default): GMRES as above; 1: the Jacobi-DIIS scheme of
  *                    Sec. 4, opening (macro-iterations X <- X + L_AB^-1 (g - L X) with DIIS,
@@ -205,10 +218,14 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    0: every solve starts from zero
  *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field kernels of the mixed
  *                    path (diagnostic: operator error of the mixed path)
- *   "m2l_waves"      wavefronts per block of the multipole-to-local kernel
- *                    (0 = chosen from the occupancy calculator; 1, 2, 4, 8, 16;
- *                    -1 = the one-node-per-block kernel built on the generic
- *                    translation, a reference for the fast kernel)
+ *   "m2l_waves"      wavefronts per block of the wavefront multipole-to-local
+ *                    kernel (0 = chosen from the occupancy calculator; 1, 2, 4,
+ *                    8, 16; -1 = the one-node-per-block kernel built on the
+ *                    generic translation, a reference for the fast kernels); a
+ *                    value other than 0 also turns the lane kernel off
+ *   "m2l_lane"       1 (default): at FMM order 12 the multipole-to-local
+ *                    translations run one per lane (Appendix translation, unrolled
+ *                    for order 12); 0: the wavefront kernel
  *   "kernel_timing"  1: record the device time of every kernel launch with HIP
  *                    events on the context's stream (see ddlpb_kernel_times)
  * Errors: EINVAL (unknown key or value out of range), ESTATE.

@@ -235,6 +235,27 @@ class Problem:
             self.q = q0
         return out
 
+    def dielectric_gradient(self, method="auto", tol=1e-12, h=1e-3):
+        """(dE/d eps_in, dE/d eps_out) by Richardson-extrapolated central differences of
+        the energy of the solved discrete problem (relative step h, error O(h^4)).  The
+        energy is a smooth function of the permittivities: they enter g through psi_0 and
+        the normal-derivative term and L through the ratio eps_in/eps_out (Sec. 2.2)."""
+        out = np.zeros(2)
+        e0 = (self.eps1, self.eps2)
+        try:
+            for k in range(2):
+                E = {}
+                for s in (-2, -1, 1, 2):
+                    eps = list(e0)
+                    eps[k] = e0[k] * (1.0 + s * h)
+                    self.eps1, self.eps2 = eps
+                    E[s] = self.solve(method, tol=tol, forces=False)["energy"]
+                step = e0[k] * h
+                out[k] = (8.0 * (E[1] - E[-1]) - (E[2] - E[-2])) / (12.0 * step)
+        finally:
+            self.eps1, self.eps2 = e0
+        return out
+
     def energy_complex_step(self, atom, coord, h=1e-30):
         """dE/dx_{atom,coord} by the complex step Im E(x + i h e)/h (dense path)."""
         d = ctypes.c_double(0.0)

@@ -18,7 +18,8 @@ EXPORTS = ["ddlpb_setup", "ddlpb_solve", "ddlpb_adjoint", "ddlpb_forces", "ddlpb
            "ddlpb_update_centers", "ddlpb_workspace_bytes", "ddlpb_bind_workspace", "ddlpb_set_stream",
            "ddlpb_get_stats", "ddlpb_strerror", "ddlpb_get_grid", "ddlpb_get_solution", "ddlpb_get_rhs",
            "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset", "ddlpb_charge_gradient",
-           "ddlpb_eval_potentials", "ddlpb_eval_potentials_noalloc"]
+           "ddlpb_eval_potentials", "ddlpb_eval_potentials_noalloc",
+           "ddlpb_dielectric_gradient"]
 
 
 class DDLPBError(RuntimeError):
@@ -58,6 +59,7 @@ def load():
         lib.ddlpb_adjoint.argtypes = [c_void_p, c_double]
         lib.ddlpb_forces.argtypes = [c_void_p, _dp]
         lib.ddlpb_charge_gradient.argtypes = [c_void_p, _dp]
+        lib.ddlpb_dielectric_gradient.argtypes = [c_void_p, _dp]
         lib.ddlpb_eval_potentials.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
         lib.ddlpb_eval_potentials_noalloc.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
         lib.ddlpb_free.argtypes = [c_void_p]
@@ -130,6 +132,13 @@ class Context:
         stream = torch.cuda.current_stream().cuda_stream
         check(load().ddlpb_set_stream(self._h, ctypes.c_void_p(stream)), "set_stream")
 
+    def use_current_stream(self):
+        """Enqueue the context's work on torch's current stream (the context keeps its
+        own device workspace, which it may enlarge when the geometry changes)."""
+        import torch
+        check(load().ddlpb_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+              "set_stream")
+
     def set_option(self, key, value):
         check(load().ddlpb_set_option(self._h, key.encode(), float(value)), f"set_option({key})")
 
@@ -176,6 +185,12 @@ class Context:
         check(fn(self._h, n, ptr(p), None if b is None else b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                  ptr(out)), "ddlpb_eval_potentials" + ("_noalloc" if noalloc else ""))
         return out[:, 0].copy(), out[:, 1].copy(), out[:, 2:5].copy(), out[:, 5:8].copy()
+
+    def dielectric_gradient(self):
+        """(dE/d eps_in, dE/d eps_out) from the adjoint solution; needs a prior adjoint."""
+        out = np.zeros(2)
+        check(load().ddlpb_dielectric_gradient(self._h, ptr(out)), "ddlpb_dielectric_gradient")
+        return out
 
     def update_centers(self, centers):
         x = np.ascontiguousarray(centers, dtype=np.float64).reshape(self.M, 3)

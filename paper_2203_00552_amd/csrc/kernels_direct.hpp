@@ -660,6 +660,18 @@ __global__ void k_axpby(long D, double a, const double* __restrict__ x, double b
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (k < D) y[k] = a * x[k] + b * y[k];
 }
+// out = (g_r - g_e, 0) [mode 0] or (g_e, g_e) [mode 1] for g = (g_r, g_e), ML entries per half
+__global__ void k_rhs_parts(long ML, int mode, const double* __restrict__ g, double* __restrict__ out) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= ML) return;
+  if (mode == 0) {
+    out[k] = g[k] - g[ML + k];
+    out[ML + k] = 0.0;
+  } else {
+    out[k] = g[ML + k];
+    out[ML + k] = g[ML + k];
+  }
+}
 // y = sum_v V[v] c[v]
 // Per-block maxima of |a - b| (b may be null: |a|) and |s + a| (s may be null: |a|):
 // part[2 block], part[2 block + 1]; grid-stride, 256 threads.

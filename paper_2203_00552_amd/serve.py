@@ -160,7 +160,8 @@ class Server:
 
 def run_arrivals(server: Server, requests, times):
     """Submit request k at time times[k] (s, from the start) and wait for all of
-    them; returns (results in request order, makespan in s)."""
+    them; returns (per request: its Result, or the exception that rejected it;
+    makespan in s, from the start to the last completion)."""
     t0 = time.perf_counter()
     futs = []
     for req, t in zip(requests, times):
@@ -168,8 +169,14 @@ def run_arrivals(server: Server, requests, times):
         if delay > 0:
             time.sleep(delay)
         futs.append(server.submit(req))
-    results = [f.result() for f in futs]
-    return results, max(r.t_done for r in results) - t0
+    results = []
+    for f in futs:
+        try:
+            results.append(f.result())
+        except Exception as e:  # rejected (invalid request, over the HBM budget)
+            results.append(e)
+    done = [r for r in results if isinstance(r, Result)]
+    return results, (max(r.t_done for r in done) - t0) if done else 0.0
 
 
 def run_poisson(server: Server, requests, rate, seed=0):
@@ -178,10 +185,24 @@ def run_poisson(server: Server, requests, rate, seed=0):
     return run_arrivals(server, requests, np.cumsum(gaps))
 
 
-def latency_summary(results, makespan):
-    lat = np.array([r.latency for r in results])
-    atoms = sum(r.atoms for r in results)
-    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "atoms_per_s": atoms / makespan,
-            "makespan_s": makespan, "atoms": atoms,
-            "not_converged": [r.rid for r in results if not r.converged]}
+def latency_summary(results, makespan, offered_atoms=None, arrival_span=None):
+    """p50/p99 latency and throughput of the served requests (entries of `results`
+    that are exceptions count as rejected); offered load when the requested atoms and
+    the arrival span are given."""
+    ok = [r for r in results if isinstance(r, Result)]
+    rejected = [(k, str(r)) for k, r in enumerate(results) if not isinstance(r, Result)]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    atoms = sum(r.atoms for r in ok)
+    conv_atoms = sum(r.atoms for r in ok if r.converged)
+    out = {"requests": len(results), "served": len(ok), "rejected": len(rejected),
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "atoms_per_s": atoms / makespan if makespan > 0 else 0.0,
+           "converged_atoms_per_s": conv_atoms / makespan if makespan > 0 else 0.0,
+           "makespan_s": makespan, "atoms": atoms,
+           "not_converged": [r.rid for r in ok if not r.converged]}
+    if rejected:
+        out["rejections"] = sorted({msg for _, msg in rejected})[:8]
+    if offered_atoms is not None and arrival_span:
+        out["offered_atoms_per_s"] = offered_atoms / arrival_span
+        out["arrival_span_s"] = arrival_span
+    return out

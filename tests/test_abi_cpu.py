@@ -50,6 +50,9 @@ def _setup(**kw):
     (dict(lmax=11), -1),
     (dict(nleb=111), -1),
     (dict(lmax=9, nleb=110), -1),   # degree 17 < 2 lmax
+    (dict(lmax=8, nleb=110), -1),   # degree 17 < 2 lmax + 2
+    (dict(lmax=7, nleb=110), 0),    # degree 17 = 2 lmax + 2
+    (dict(lmax=8, nleb=146), 0),
     (dict(x=np.array([[0, 0, 0], [0, 0, 0]])), -2),
     (dict(M=0), -1),
 ])

@@ -26,27 +26,37 @@ def test_backward_is_minus_oracle_forces():
     model.close()
 
 
-def test_backward_matches_central_differences():
-    """Central differences (h = 1e-4 A) of the FP64 direct-sum energy on 20 seeded
-    atoms x 3 coordinates of a 300-atom cluster."""
-    x, r, q = inputs.lattice_cluster(300, seed=8)
-    model = DDLPBEnergy(r, q, tol=1e-11, lmax=6, n_lebedev=110)
+def test_backward_matches_central_differences_config4():
+    """Central differences (h = 1e-4 A) of the FP64 direct-sum energy of the 2,000-atom
+    cluster (lattice generator, seed 0; lmax 8, 302 points) on 20 atoms chosen with
+    seed 1 x 3 coordinates, against the backward pass.  A coordinate whose +-h
+    perturbation moves a grid point across f = 1 (where U has a kink, so the energy is
+    only piecewise C^1) is skipped and counted; the solves are warm-started."""
+    x, r, q = inputs.lattice_cluster(2000, seed=0)
+    model = DDLPBEnergy(r, q, tol=1e-12, lmax=8, n_lebedev=302)
     X = torch.tensor(x, dtype=torch.float64, requires_grad=True)
     model(X).backward()
     g = X.grad.numpy()
-    rng = np.random.default_rng(9)
-    atoms = rng.choice(len(r), 20, replace=False)
+    atoms = np.random.default_rng(1).choice(len(r), 20, replace=False)
     h = 1e-4
-    err = 0.0
+    err, skipped = 0.0, 0
     with torch.no_grad():
         for a in atoms:
             for c in range(3):
-                xp, xm = x.copy(), x.copy()
-                xp[a, c] += h
-                xm[a, c] -= h
-                fd = (model(torch.tensor(xp)).item() - model(torch.tensor(xm)).item()) / (2 * h)
-                err = max(err, abs(fd - g[a, c]))
-    assert err < 1e-5 * np.abs(g).max(), err
+                E, side = [], []
+                for sgn in (1.0, -1.0):
+                    xs = x.copy()
+                    xs[a, c] += sgn * h
+                    E.append(model(torch.tensor(xs)).item())
+                    side.append(model._slots[0].ctx.grid()[0] > 1.0)
+                if np.any(side[0] != side[1]):
+                    skipped += 1
+                    continue
+                err = max(err, abs((E[0] - E[1]) / (2 * h) - g[a, c]))
+    print(f"config 4 finite differences: max error {err / np.abs(g).max():.2e} of max|grad|, "
+          f"{skipped} of 60 coordinates skipped at f = 1")
+    assert skipped <= 10
+    assert err < 2e-5 * np.abs(g).max(), err
     model.close()
 
 

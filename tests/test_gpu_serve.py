@@ -9,17 +9,20 @@ from paper_2203_00552_amd.serve import Request, Server, latency_summary, run_poi
 pytestmark = pytest.mark.gpu
 
 
-def _requests():
-    spec = [(60, 6, 110), (900, 8, 302), (2500, 8, 302), (300, 6, 302), (1500, 6, 110), (120, 8, 110)]
+def _requests(precision=0):
+    spec = [(60, 6, 110), (900, 8, 302), (2500, 8, 302), (300, 6, 302), (1500, 6, 110), (120, 8, 146)]
     out = []
     for k, (n, lmax, nleb) in enumerate(spec):
         x, r, q = inputs.lattice_cluster(n, seed=100 + k)
-        out.append(Request(x, r, q, lmax=lmax, n_lebedev=nleb, tol=1e-8, rid=k))
+        out.append(Request(x, r, q, lmax=lmax, n_lebedev=nleb, tol=1e-8, precision=precision, rid=k))
     return out
 
 
-def test_alone_equals_mix():
-    reqs = _requests()
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_mix(precision):
+    """FP64 and the mixed path (FP32 preconditioner sweeps): bitwise-deterministic
+    kernels, so every result is the same alone and among concurrent requests."""
+    reqs = _requests(precision)
     alone = []
     s1 = Server(slots=1)
     for rq in reqs:
@@ -43,3 +46,17 @@ def test_poisson_latency_summary():
     s.close()
     summ = latency_summary(res, span)
     assert summ["requests"] == 4 and summ["p99_ms"] >= summ["p50_ms"] > 0
+
+
+def test_underresolved_grid_is_rejected():
+    """lmax 8 on the 110-point grid (quadrature degree 17 < 2 lmax + 2) is rejected at
+    setup (EINVAL) instead of stagnating in the solver; the other requests are served."""
+    from paper_2203_00552_amd.serve import run_arrivals
+    x, r, q = inputs.lattice_cluster(200, seed=5)
+    reqs = [Request(x, r, q, lmax=8, n_lebedev=110, rid=0), Request(x, r, q, lmax=8, n_lebedev=302, rid=1)]
+    s = Server(slots=2)
+    res, span = run_arrivals(s, reqs, [0.0, 0.0])
+    s.close()
+    assert isinstance(res[0], Exception) and getattr(res[0], "code", None) == -1
+    summ = latency_summary(res, span)
+    assert summ["served"] == 1 and summ["rejected"] == 1 and not summ["not_converged"]

@@ -480,3 +480,28 @@ def test_single_layer_addition_theorem(kappa):
     assert act.sum() > 500
     assert np.abs(Phi[~act]).max() == 0.0
     assert np.abs(Phi[act] - ref[act]).max() < 1e-10 * np.abs(ref[act]).max()
+
+
+# ------------------------------------------------------- permittivity gradient
+def test_dielectric_gradient_single_sphere_closed_form():
+    """E = q^2/(2a) (1/(eps_out (1 + kappa a)) - 1/eps_in) for one sphere with a centred
+    charge, so dE/d eps_in = q^2/(2 a eps_in^2) and dE/d eps_out =
+    -q^2/(2 a eps_out^2 (1 + kappa a))."""
+    a, q, kap, e1, e2 = 1.7, 0.8, 0.104, 2.0, 60.0
+    P = oracle.Problem([[0.3, 0.1, -0.2]], [a], [q], e1, e2, kap, lmax=4, n_lebedev=110)
+    g = P.dielectric_gradient("dense")
+    ref = [q * q / (2 * a * e1 * e1), -q * q / (2 * a * e2 * e2 * (1 + kap * a))]
+    np.testing.assert_allclose(g, ref, rtol=1e-9)
+
+
+def test_dielectric_gradient_euler_identity():
+    """The operator depends on the permittivities only through eps_in/eps_out and the
+    right-hand side scales as 1/eps (psi_0 ~ 1/eps_in, the normal-derivative term
+    ~ 1/eps_out), so E(s eps_in, s eps_out) = E/s: eps_in dE/d eps_in + eps_out dE/d
+    eps_out = -E.  Both partial derivatives are nonzero and of either sign."""
+    x, r, q = inputs.small_cluster(1)
+    P = oracle.Problem(x, r, q, 1.5, 78.54, 0.104, lmax=4, n_lebedev=110)
+    g = P.dielectric_gradient("dense")
+    E = P.solve("dense", forces=False)["energy"]
+    assert abs((P.eps1 * g[0] + P.eps2 * g[1]) / -E - 1) < 1e-9
+    assert g[0] > 0 and g[1] < 0
