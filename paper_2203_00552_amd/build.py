@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddlpb.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("ddlpb.hip", "m2l_lane_yf.hip", "m2l_lane_yt.hip", "m2l_lane_lf.hip", "m2l_lane_lt.hip")]
+           ("ddlpb.hip", "near_lane.hip", "m2l_lane_yf.hip", "m2l_lane_yt.hip", "m2l_lane_lf.hip", "m2l_lane_lt.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-pthread"]

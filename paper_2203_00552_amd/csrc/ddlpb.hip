@@ -25,6 +25,7 @@
 #include "fmm.hpp"
 #include "fmm_host.hpp"
 #include "fmm_lane_api.hpp"
+#include "near_lane_api.hpp"
 
 using namespace ddlpb;
 
@@ -63,6 +64,7 @@ void ensure_constants() {
   for (int l = 0; l <= kLmaxDev + 1; ++l)
     for (int k = 0; k < kSigTerms; ++k) sinv[l * kSigTerms + k] = 0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_sinv), sinv.data(), sinv.size() * sizeof(double)));
+  HIPCHK(nearlane::upload_tables(pmm.data(), ra.data(), rb.data()));
   g_const_done[dev] = true;
 }
 
@@ -92,6 +94,14 @@ struct ddlpb_ctx {
   double theta = 0.6;
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic, -1: block kernel)
   int m2l_lane = 1;           // order 12: the one-translation-per-lane M2L kernels (when m2l_waves is 0)
+  int near_lane = 1;          // lmax <= 8: the near-field A/B kernels with one cap per lane
+  int near_incore = 0;        // with near_lane: harmonics of every reverse cap kept in device memory
+  bool use_lane = false;      // lane kernels set up for the current geometry
+  int* d_f2r = nullptr;       // forward cap -> its position in the reverse lists
+  double* d_capv = nullptr;   // (A, B) value pair of every reverse cap, [2 cap_cap]
+  long* d_coff = nullptr;     // incore cache: first (padded) cap position of every sphere
+  double* d_cache = nullptr;  // incore cache (owned by the context, outside the workspace)
+  size_t cache_bytes = 0;
   int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
   struct M2LCfg { bool valid = false, alds = false; int nw = 0, per_cu = 0; size_t bytes = 0; } m2l_cfg[2];
   // ---- host analysis
@@ -378,6 +388,9 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_rci = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
   c->d_rcn = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
   c->d_rcw = cv.take<double>(std::max<size_t>(c->cap_cap, 1));
+  c->d_f2r = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
+  c->d_capv = cv.take<double>(2 * std::max<size_t>(c->cap_cap, 1));
+  c->d_coff = cv.take<long>(M);
   c->d_pidx = cv.take<int>(std::max<size_t>(c->pnz_cap, 1));
   // dot-product scratch: the outer basis, the inner GMRES of either preconditioner and
   // the DIIS histories all call mdot with at most this many vectors
@@ -575,6 +588,8 @@ void sl_adjoint(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, dou
   HIPCHK(hipGetLastError());
 }
 
+void an_gemm(ddlpb_ctx* c, const double* base, double c0, double* out);
+nearlane::NearArgs near_args(ddlpb_ctx* c);
 // near-field A/B kernels over the cap lists in compute type R (float on the mixed path)
 template <class R>
 void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
@@ -591,8 +606,10 @@ void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* n
                        gr2, ge, cg, out, gemm ? c->d_Vpt : nullptr);
   });
   HIPCHK(hipGetLastError());
-  if (!gemm) return;
-  // out = c0 base + An(point values): (L x 2M) = WY (L x N) x Vpt (N x 2M), column-major
+  if (gemm) an_gemm(c, base, c0, out);
+}
+// out = c0 base + An(point values in d_Vpt): (L x 2M) = WY (L x N) x Vpt (N x 2M), column-major
+void an_gemm(ddlpb_ctx* c, const double* base, double c0, double* out) {
   const long D = 2L * c->M * c->L;
   double beta = 0.0;
   if (base == out) {
@@ -623,6 +640,24 @@ void launch_LTZ_caps(ddlpb_ctx* c, const double* base, double c0, const double* 
 
 void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, double c1, const double* gr1,
               const double* gr2, const double* ge, double cg, double* out) {
+  if (c->use_lane) {
+    // per-cap values by the sphere that owns the harmonics, per-point sums in forward
+    // order, then the An transforms of all spheres as one GEMM
+    if (nearX) {
+      KScope ks(c, c->cur_prec == 1 ? "near_lx_f32" : "near_lx", flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap);
+      HIPCHK(nearlane::launch_lx(c->lmax, c->cur_prec, near_args(c), nearX, c->d_capv, c->stream));
+    }
+    {
+      KScope ks(c, "near_point_sums", 0.0);
+      const long MN = (long)c->M * c->N;
+      hipLaunchKernelGGL(k_point_sums, dim3(nblk(MN, 256)), dim3(256), 0, c->stream, c->M, c->N, c->d_pcp, c->d_f2r,
+                         nearX ? c->d_capv : nullptr, c1, c->d_U, gr1, gr2, ge, cg, c->d_Vpt);
+      HIPCHK(hipGetLastError());
+    }
+    KScope ks(c, "an_gemm", 2.0 * c->N * c->L * 2.0 * c->M);
+    an_gemm(c, base, c0, out);
+    return;
+  }
   KScope ks(c, "apply_LX", nearX ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
     if (c->cur_prec == 1) launch_LX_caps<float>(c, base, c0, nearX, c1, gr1, gr2, ge, cg, out);
@@ -654,6 +689,21 @@ void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
 
 void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
                const double* lam, int llam, double* out) {
+  if (c->use_lane) {
+    {
+      KScope ks(c, c->cur_prec == 1 ? "near_ltz_f32" : "near_ltz",
+                zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
+      HIPCHK(nearlane::launch_ltz(c->lmax, c->cur_prec, near_args(c), base, c0, zr, ze, c1, out, c->stream));
+    }
+    if (lam) {
+      KScope ks(c, "sl_adjoint_part", 4.0 * c->N * c->L * (double)c->M);
+      LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_lam_add<LMc>), dim3(c->M), dim3(128), (c->L + c->N) * sizeof(double),
+                                              c->stream, c->M, c->N, c->LY, c->d_Y, c->d_YT, c->d_leb, c->d_U, c->d_ycr,
+                                              c->d_yce, c->d_Cl, c->LUR, lam, llam, out));
+      HIPCHK(hipGetLastError());
+    }
+    return;
+  }
   KScope ks(c, "apply_LTZ", zr ? flops_cap_pair(c->lmax, c->nterms) * (double)c->ncap : 0.0);
   if (c->use_caps) {
     if (c->cur_prec == 1) launch_LTZ_caps<float>(c, base, c0, zr, ze, c1, lam, llam, out);
@@ -1582,6 +1632,65 @@ void upload_tree(ddlpb_ctx* c) {
   c->stats.n_near_pairs = (int64_t)t.near_idx.size();
 }
 
+nearlane::NearArgs near_args(ddlpb_ctx* c) {
+  nearlane::NearArgs a;
+  a.M = c->M;
+  a.N = c->N;
+  a.LUR = c->LUR;
+  a.nterms = c->nterms;
+  a.kappa = c->kappa;
+  a.leb = c->d_leb;
+  a.xyz = c->d_xyz;
+  a.rad = c->d_rad;
+  a.rptr = c->d_rptr;
+  a.rci = c->d_rci;
+  a.rcn = c->d_rcn;
+  a.rcw = c->d_rcw;
+  a.isgr = c->d_isgr;
+  a.cache = c->near_incore ? c->d_cache : nullptr;
+  a.coff = c->d_coff;
+  return a;
+}
+
+// The lane kernels need every forward cap's position in the reverse lists (for the
+// per-point sums of the forward pass) and, with near_incore, the cache of harmonics.
+// rcnt: reverse caps per sphere; nrev: their total.
+void setup_lane(ddlpb_ctx* c, const std::vector<int>& rcnt, long nrev) {
+  const int M = c->M, N = c->N;
+  c->use_lane = false;
+  if (!c->near_lane || c->lmax > nearlane::kMaxLm || nrev != c->ncap) return;
+  HIPCHK(hipMemsetAsync(c->d_actcnt, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_cap_perm, dim3(nblk(M, 64)), dim3(64), 0, c->stream, M, N, c->d_nptr, c->d_nidx, c->d_rptr,
+                     c->d_rci, c->d_rcn, c->d_pcp, c->d_capslot, c->d_f2r, c->d_actcnt);
+  HIPCHK(hipGetLastError());
+  int found = 0;
+  HIPCHK(hipMemcpyAsync(&found, c->d_actcnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (found != c->ncap) return;  // forward and reverse lists disagree: keep the cap kernels
+  c->use_lane = true;
+  if (!c->near_incore) return;
+  // incore: sphere j's caps at padded position coff[j] (a multiple of 16)
+  std::vector<long> coff(M);
+  long tot = 0;
+  for (int j = 0; j < M; ++j) {
+    coff[j] = tot;
+    tot += (rcnt[j] + nearlane::kGroup - 1) / nearlane::kGroup * nearlane::kGroup;
+  }
+  const size_t need = std::max<size_t>((size_t)tot * nearlane::cache_stride(c->lmax) * sizeof(double), 256);
+  if (need > c->cache_bytes) {
+    if (c->d_cache) HIPCHK(hipFree(c->d_cache));
+    c->d_cache = nullptr;
+    c->cache_bytes = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) throw std::bad_alloc();
+    c->d_cache = (double*)p;
+    c->cache_bytes = need;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_coff, coff.data(), M * sizeof(long), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(nearlane::launch_fill(c->lmax, near_args(c), c->d_cache, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
 void geometry_on_device(ddlpb_ctx* c) {
   const int M = c->M, N = c->N;
   HIPCHK(hipMemcpyAsync(c->d_xyz, c->x.data(), 3 * M * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1631,6 +1740,9 @@ void geometry_on_device(ddlpb_ctx* c) {
     hipLaunchKernelGGL(k_rcaps_fill, dim3(nblk(M, 64)), dim3(64), 0, c->stream, M, N, c->d_xyz, c->d_rad, c->d_leb,
                        c->d_nptr, c->d_nidx, c->d_f, c->eta, c->d_rptr, c->d_rci, c->d_rcn, c->d_rcw);
     HIPCHK(hipGetLastError());
+    setup_lane(c, cnt, cp[M]);
+  } else {
+    c->use_lane = false;
   }
   hipLaunchKernelGGL(k_active_fill, dim3(nblk(M, 128)), dim3(128), 0, c->stream, M, N, c->d_U, c->d_actptr,
                      c->d_actsph, c->d_actn);
@@ -2070,6 +2182,7 @@ void ddlpb_free(ddlpb_ctx* c) {
   if (!c) return;
   if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+  if (c->d_cache) (void)hipFree(c->d_cache);
   for (auto& p : c->ev_pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -2124,6 +2237,11 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "m2l_lane") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->m2l_lane = (int)v;
+  } else if (k == "near_lane" || k == "near_incore") {
+    // cap structures depend on both: set before the first device call
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    (k == "near_lane" ? c->near_lane : c->near_incore) = (int)v;
   } else if (k == "solver") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->solver = (int)v;

@@ -796,6 +796,88 @@ __global__ void k_rcaps_fill(int M, int N, const double* __restrict__ xyz, const
   }
 }
 
+// Position in the reverse lists of every forward cap: the reverse cap (j; i, n) is the
+// forward cap of point (i, n) whose neighbour slot names j.  found counts the matches
+// (the host checks that every cap was matched).
+__global__ void k_cap_perm(int M, int N, const int* __restrict__ nptr, const int* __restrict__ nidx,
+                           const int* __restrict__ rptr, const int* __restrict__ rc_i, const int* __restrict__ rc_n,
+                           const int* __restrict__ pcp, const int* __restrict__ cap_slot, int* __restrict__ f2r,
+                           int* __restrict__ found) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int cnt = 0;
+  for (int r = rptr[j]; r < rptr[j + 1]; ++r) {
+    const int i = rc_i[r], n = rc_n[r];
+    const long pp = (long)i * (N + 1) + n;
+    for (int f = pcp[pp]; f < pcp[pp + 1]; ++f)
+      if (nidx[nptr[i] + cap_slot[f]] == j) {
+        f2r[f] = r;
+        ++cnt;
+        break;
+      }
+  }
+  atomicAdd(found, cnt);
+}
+
+// Point values of the near part from the per-cap values of the lane kernel: for every
+// grid point, the sum over its caps in forward-list order, plus the grid terms
+// (U (gr1 + gr2) and U ge, scaled by cg); Vpt [2M][N] is the input of the An GEMM.
+__global__ void k_point_sums(int M, int N, const int* __restrict__ pcp, const int* __restrict__ f2r,
+                             const double* __restrict__ capv, double c1, const double* __restrict__ U,
+                             const double* __restrict__ gr1, const double* __restrict__ gr2,
+                             const double* __restrict__ ge, double cg, double* __restrict__ Vpt) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long MN = (long)M * N;
+  if (idx >= MN) return;
+  const int i = (int)(idx / N), n = (int)(idx - (long)i * N);
+  double a = 0.0, b = 0.0;
+  if (capv) {
+    const long pp = (long)i * (N + 1) + n;
+    for (int f = pcp[pp]; f < pcp[pp + 1]; ++f) {
+      const double2 v = *reinterpret_cast<const double2*>(capv + 2L * f2r[f]);
+      a += v.x;
+      b += v.y;
+    }
+  }
+  const double u = U[idx];
+  const double gR = gr1 ? u * (gr1[idx] + (gr2 ? gr2[idx] : 0.0)) : 0.0;
+  const double gE = ge ? u * ge[idx] : 0.0;
+  Vpt[idx] = c1 * a + cg * gR;
+  Vpt[MN + idx] = c1 * b + cg * gE;
+}
+
+// The single-layer part of the transposed operator for the coefficients lam of every
+// sphere j: mu = An_j(U_j Syn(C_l lam_j)); out_r += ycr_l mu, out_e += yce_l mu.
+// One block of 128 threads per sphere; dynamic LDS of L + N doubles.
+template <int LM>
+__global__ __launch_bounds__(128) void k_lam_add(int M, int N, int LY, const double* __restrict__ Y,
+                                                 const double* __restrict__ YT, const double* __restrict__ leb,
+                                                 const double* __restrict__ U, const double* __restrict__ ycr,
+                                                 const double* __restrict__ yce, const double* __restrict__ Cl,
+                                                 int LUR, const double* __restrict__ lam, int LLAM,
+                                                 double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  extern __shared__ double sh_raw[];
+  double* cl = sh_raw;
+  double* gg = cl + L;
+  const int j = blockIdx.x;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) cl[t] = Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t];
+  __syncthreads();
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    double a = 0.0;
+    for (int t = 0; t < L; ++t) a += YT[(long)t * N + n] * cl[t];
+    gg[n] = U[(long)j * N + n] * a;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double a = 0.0;
+    for (int n = 0; n < N; ++n) a += leb[4 * n + 3] * Y[(long)n * LY + t] * gg[n];
+    const int l = deg_of(t);
+    out[(long)j * L + t] += ycr[j * LUR + l] * a;
+    out[(long)(M + j) * L + t] += yce[j * LUR + l] * a;
+  }
+}
+
 // ------------------------------------------- apply L (near part) from cap lists
 // Same result as k_apply_LX: one block per sphere i.  Each cap is evaluated by four
 // lanes (the harmonic columns m = q mod 4 of lane q, see solid_harmonic_quad) and
