@@ -252,11 +252,11 @@ def main():
     # roofline of the three kernels with the most device time (labels pass_* time whole FMM
     # passes, not one kernel); work = the library's count of algorithmic flops per launch
     # (the design doc, section 8), time = HIP events on the context's stream
-    fp32_labels = ("apply_LX", "apply_LTZ")
+    fp32_labels = ("apply_LX", "apply_LTZ")  # cap-list kernels: one label for both precisions
     tops = sorted(((k, v) for k, v in kt.items() if not k.startswith("pass_")), key=lambda kv: -kv[1][0])[:3]
 
     def roof(name, ms, nl, work):
-        fp32 = args.precision != "fp64" and name in fp32_labels
+        fp32 = name.endswith("_f32") or (args.precision != "fp64" and name in fp32_labels)
         peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
         achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -291,6 +291,7 @@ def main():
         mctx = make(PRECISION["mixed"])
         Em, Fm, dtm = timed(mctx, args.mixed_steps, 0, "mixed")
         mst = mctx.stats()
+        mkt = mctx.kernel_times()
         mctx.close()
         out["mixed"] = {"value": atoms * args.mixed_steps / dtm, "unit": "atoms/s",
                         "ms_per_step": dtm * 1e3 / args.mixed_steps,
@@ -298,7 +299,9 @@ def main():
                         "energy_rel_err_vs_fp64": abs(Em - E) / abs(E),
                         "force_rel_err_vs_fp64": float(np.abs(Fm - F).max() / np.abs(F).max()),
                         "iters": [mst["iters_primal"], mst["iters_adjoint"]],
-                        "residuals": [mst["resid_primal"], mst["resid_adjoint"]]}
+                        "residuals": [mst["resid_primal"], mst["resid_adjoint"]],
+                        "kernels_ms_per_step": {k: v[0] / args.mixed_steps
+                                                for k, v in sorted(mkt.items(), key=lambda kv: -kv[1][0])[:12]}}
         log("mixed leg done")
     if args.serve_requests > 0:
         log(f"serving run: {args.serve_requests} requests")

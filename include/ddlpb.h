@@ -226,6 +226,18 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "m2l_lane"       1 (default): at FMM order 12 the multipole-to-local
  *                    translations run one per lane (Appendix translation, unrolled
  *                    for order 12); 0: the wavefront kernel
+ *   "near_lane"      1 (default): for lmax <= 8 the near-field A/B couplings
+ *                    (Sec. 2.2, A_ij and B_ij) run one neighbour cap per lane,
+ *                    grouped by the sphere whose basis functions are evaluated;
+ *                    0: the cap-list kernels (always used for lmax > 8).  Set
+ *                    before the first solve (else ESTATE).
+ *   "near_incore"    1: with near_lane, the harmonics and radial ratios of every
+ *                    cap are computed once per geometry and kept in device memory
+ *                    ((lmax+1)^2 + lmax + 1 doubles per cap, allocated by the
+ *                    library outside the workspace; ENOMEM if it does not fit)
+ *                    instead of being recomputed in every application (the
+ *                    paper's "incore" variant of the sparse products, Sec. 4).
+ *                    Set before the first solve (else ESTATE).
  *   "kernel_timing"  1: record the device time of every kernel launch with HIP
  *                    events on the context's stream (see ddlpb_kernel_times)
  * Errors: EINVAL (unknown key or value out of range), ESTATE.

@@ -51,6 +51,13 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2203_00552_amd.build.build()")
+        # torch ships its own HIP runtime under the same soname as the system one: load it
+        # first, so that the library binds to it and the process holds one runtime (torch
+        # cannot initialise the device after another runtime has)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         c_void_p, c_int, c_double, c_size_t = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
         lib.ddlpb_setup.argtypes = [c_int, _dp, _dp, _dp, c_double, c_double, c_double, c_int, c_int, c_int,

@@ -68,6 +68,36 @@ void ensure_constants() {
   g_const_done[dev] = true;
 }
 
+// Internal order of the Lebedev points: the leaves of a recursive bisection (split at
+// the median of the coordinate with the largest spread), so that the points of a
+// spherical cap -- the grid points of a sphere inside a neighbour -- have few runs of
+// consecutive indices and reads of per-point data by cap are coalesced.  Every sum
+// over the points is independent of the order up to rounding.
+void order_points(const double* xyzw, int N, std::vector<int>& ord) {
+  ord.resize(N);
+  for (int n = 0; n < N; ++n) ord[n] = n;
+  std::function<void(int, int)> split = [&](int lo, int hi) {
+    if (hi - lo <= 2) return;
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int k = lo; k < hi; ++k)
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = std::min(mn[a], xyzw[4 * ord[k] + a]);
+        mx[a] = std::max(mx[a], xyzw[4 * ord[k] + a]);
+      }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (mx[a] - mn[a] > mx[ax] - mn[ax]) ax = a;
+    std::sort(ord.begin() + lo, ord.begin() + hi, [&](int p, int q) {
+      const double a = xyzw[4 * p + ax], b = xyzw[4 * q + ax];
+      return a < b || (a == b && p < q);
+    });
+    const int mid = (lo + hi) / 2;
+    split(lo, mid);
+    split(mid, hi);
+  };
+  split(0, N);
+}
+
 }  // namespace
 
 struct ddlpb_ctx {
@@ -76,6 +106,10 @@ struct ddlpb_ctx {
   double eps1 = 1, eps2 = 78.54, kappa = 0.1, eta = 0.05;
   std::vector<double> x, r, q;
   const ddlpb_tables::LebedevRule* rule = nullptr;
+  // the rule's points and weights in the library's internal order (spatially coherent,
+  // see order_points) and the rule's index of every internal point
+  std::vector<double> leb;
+  std::vector<int> leb_orig;
   // ---- options
   int precision = 0, restart = 100, sweeps = 1, maxit = 400;
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
@@ -1537,7 +1571,7 @@ void upload_and_init(ddlpb_ctx* c) {
   std::vector<double> Y((size_t)N * c->LY);
   const int ydeg = (int)std::lround(std::sqrt((double)c->LY)) - 1;
   for (int n = 0; n < N; ++n) {
-    const double* s = c->rule->xyzw + 4 * n;
+    const double* s = c->leb.data() + 4 * n;
     host::solid_harmonics<double>(ydeg, s[0], s[1], s[2], &Y[(size_t)n * c->LY]);
   }
   std::vector<double> dtab;
@@ -1548,7 +1582,7 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_xyz, c->x.data(), 3 * M * sizeof(double));
   up(c->d_rad, c->r.data(), M * sizeof(double));
   up(c->d_q, c->q.data(), M * sizeof(double));
-  up(c->d_leb, c->rule->xyzw, 4 * N * sizeof(double));
+  up(c->d_leb, c->leb.data(), 4 * N * sizeof(double));
   up(c->d_Y, Y.data(), Y.size() * sizeof(double));
   std::vector<double> YT(Y.size());
   for (int n = 0; n < N; ++n)
@@ -1556,7 +1590,7 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_YT, YT.data(), YT.size() * sizeof(double));
   std::vector<double> WY((size_t)N * c->L);
   for (int n = 0; n < N; ++n)
-    for (int t = 0; t < c->L; ++t) WY[(size_t)n * c->L + t] = c->rule->xyzw[4 * n + 3] * Y[(size_t)n * c->LY + t];
+    for (int t = 0; t < c->L; ++t) WY[(size_t)n * c->L + t] = c->leb[4 * n + 3] * Y[(size_t)n * c->LY + t];
   up(c->d_WY, WY.data(), WY.size() * sizeof(double));
   up(c->d_nptr, c->nptr.data(), (M + 1) * sizeof(int));
   up(c->d_nidx, c->nidx.data(), c->nidx.size() * sizeof(int));
@@ -1839,6 +1873,10 @@ int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, con
     c->LUR = lmax + 2;
     c->N = n_lebedev;
     c->rule = host::lebedev_rule(n_lebedev);
+    order_points(c->rule->xyzw, n_lebedev, c->leb_orig);
+    c->leb.resize(4 * (size_t)n_lebedev);
+    for (int n = 0; n < n_lebedev; ++n)
+      for (int k = 0; k < 4; ++k) c->leb[4 * (size_t)n + k] = c->rule->xyzw[4 * (size_t)c->leb_orig[n] + k];
     c->fmm_order = fmm_order;
     c->eps1 = eps_in; c->eps2 = eps_out; c->kappa = kappa;
     c->x.assign(centers, centers + 3L * n_atoms);
@@ -2413,10 +2451,18 @@ int ddlpb_get_grid(ddlpb_ctx* c, double* f_out, double* u_out) {
   return guarded([&]() -> int {
     int rc = ensure_device(c);
     if (rc) return rc;
-    const size_t MN = (size_t)c->M * c->N;
-    if (f_out) HIPCHK(hipMemcpyAsync(f_out, c->d_f, MN * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    if (u_out) HIPCHK(hipMemcpyAsync(u_out, c->d_U, MN * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    const int M = c->M, N = c->N;
+    const size_t MN = (size_t)M * N;
+    std::vector<double> tmp(MN);
+    for (int k = 0; k < 2; ++k) {  // back to the rule's point order
+      double* dst = k == 0 ? f_out : u_out;
+      if (!dst) continue;
+      HIPCHK(hipMemcpyAsync(tmp.data(), k == 0 ? c->d_f : c->d_U, MN * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int i = 0; i < M; ++i)
+        for (int n = 0; n < N; ++n) dst[(size_t)i * N + c->leb_orig[n]] = tmp[(size_t)i * N + n];
+    }
     return DDLPB_OK;
   });
 }
