@@ -1147,7 +1147,8 @@ void precond(ddlpb_ctx* c, bool transpose, const double* v, double* z) {
 void mdot(ddlpb_ctx* c, int nv, const double* V, long ldv, const double* w, double* h_host) {
   const long D = 2L * c->M * c->L;
   if (nv < 1 || nv > c->mk) throw HipError{hipErrorInvalidValue};  // scratch holds mk vectors
-  hipLaunchKernelGGL(k_mdot_part, dim3(c->nb_dot, nv), dim3(256), 0, c->stream, D, nv, V, ldv, w, c->d_part);
+  hipLaunchKernelGGL(k_mdot_part, dim3(c->nb_dot, (nv + kDotV - 1) / kDotV), dim3(256), 0, c->stream, D, nv, V, ldv, w,
+                     c->d_part);
   hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(256), 0, c->stream, c->nb_dot, c->d_part, c->d_hv);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h_host, c->d_hv, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));

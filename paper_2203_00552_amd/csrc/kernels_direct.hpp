@@ -622,17 +622,35 @@ __global__ __launch_bounds__(256) void k_apply_LTZ(int M, int N, int LY, const d
 
 // ---------------------------------------------------------- Krylov helpers
 // part[v * nb + b] = sum over block b's range of V[v][k] * w[k]
+// Partial dot products of kDotV vectors V[v0 .. v0+kDotV) (stride ldv) with w over one
+// chunk of D per block: w is read once for kDotV vectors.  part[v * gridDim.x + block].
+constexpr int kDotV = 8;
 __global__ __launch_bounds__(256) void k_mdot_part(long D, int nv, const double* __restrict__ V, long ldv,
                                                     const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[16];
-  const int v = blockIdx.y;
+  __shared__ double sh[kDotV][4];
+  const int v0 = blockIdx.y * kDotV, nvb = min(kDotV, nv - v0);
   const long chunk = (D + gridDim.x - 1) / gridDim.x;
   const long k0 = blockIdx.x * chunk, k1 = min(D, k0 + chunk);
-  double s = 0.0;
-  const double* Vv = V + v * ldv;
-  for (long k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += Vv[k] * w[k];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(long)v * gridDim.x + blockIdx.x] = s;
+  double s[kDotV];
+#pragma unroll
+  for (int u = 0; u < kDotV; ++u) s[u] = 0.0;
+  const double* Vv = V + (long)v0 * ldv;
+  for (long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const double wk = w[k];
+#pragma unroll
+    for (int u = 0; u < kDotV; ++u)
+      if (u < nvb) s[u] += Vv[u * ldv + k] * wk;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;  // blockDim.x == 256
+#pragma unroll
+  for (int u = 0; u < kDotV; ++u) {
+    const double t = wave_sum(s[u]);
+    if (lane == 0) sh[u][wid] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < nvb)
+    part[(long)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+        ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
 }
 __global__ __launch_bounds__(256) void k_mdot_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double sh[16];
