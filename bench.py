@@ -11,6 +11,7 @@ charges N(0, 0.3) neutralised), lmax 8, 302 Lebedev points, tolerance 1e-6.
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -60,6 +61,8 @@ def parse():
                         "mixed-refine: FP32 operator inside FP64 iterative refinement")
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--probe-radius", type=float, default=0.0,
+                   help="add this to every radius (1.4: solvent-accessible radii, many more caps)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--serve-requests", type=int, default=512,
                    help="requests of the serving run (0: skip); the serving workload has 512")
@@ -118,7 +121,25 @@ def cpu_baseline(args, n_c, n_ab, atoms):
     t_ab = time.perf_counter() - t0
     scale = atoms / n
     seconds = n_c * t_c * scale * scale + n_ab * t_ab * scale
+    # the same two applications on one core, at 300 atoms (a child process, so that its
+    # OpenMP runtime starts with one thread; it does not touch the GPU)
+    n1 = 300
+    code = ("import time, numpy as np, oracle\n"
+            "from paper_2203_00552_amd import inputs\n"
+            f"x, r, q = inputs.lattice_cluster({n1}, seed={args.seed})\n"
+            f"P = oracle.Problem(x, r, q, lmax={args.lmax}, n_lebedev={args.nleb})\n"
+            f"X = np.random.default_rng(1).normal(size=(2, {n1}, P.L))\n"
+            "t0 = time.perf_counter(); P.apply(X, part='C'); t1 = time.perf_counter(); P.apply(X, part='AB')\n"
+            "print(t1 - t0, time.perf_counter() - t1)\n")
+    one = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=dict(os.environ, OMP_NUM_THREADS="1"),
+                         capture_output=True, text=True, timeout=600)
+    t1c, t1ab = (float(v) for v in one.stdout.split()[-2:])
+    s1 = atoms / n1
+    seconds_1 = n_c * t1c * s1 * s1 + n_ab * t1ab * s1
     return {"value": atoms / seconds, "unit": "atoms/s", "cores": threads, "physical_cores": physical_cores(),
+            "one_core": {"value": atoms / seconds_1, "unit": "atoms/s", "cores": 1,
+                         "sample": f"single-layer apply {t1c:.2f} s and A/B apply {t1ab:.3f} s at {n1} atoms, "
+                                   f"scaled the same way: {seconds_1 / 3600:.3g} h per step"},
             "kind": "oracle", "extrapolated": True,
             "sample": f"oracle single-layer apply {t_c:.1f} s and A/B apply {t_ab:.2f} s at 1,000 atoms (same "
                       f"generator, lmax {args.lmax}, {args.nleb} points), scaled to {atoms} atoms by M^2 and M and "
@@ -213,6 +234,7 @@ def main():
     fmm = args.fmm_order if args.fmm_order is not None else 12
     atoms = args.atoms if args.atoms is not None else 100000
     x, r, q = inputs.lattice_cluster(atoms, seed=args.seed)
+    r = r + args.probe_radius
     log(f"generated {atoms} atoms")
     torch.cuda.init()
     extra = {kv.split("=")[0]: float(kv.split("=")[1]) for kv in args.option}
@@ -275,12 +297,13 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"jittered-lattice cluster, {atoms} atoms, lmax {args.lmax}, {args.nleb} Lebedev "
-                               f"points, tol {args.tol:g}, " + (f"FMM p={fmm}" if fmm else "direct sums"),
+                               f"points, tol {args.tol:g}, " + (f"FMM p={fmm}" if fmm else "direct sums")
+                               + (f", radii +{args.probe_radius:g} A" if args.probe_radius else ""),
                    "atoms": atoms, "lmax": args.lmax, "n_lebedev": args.nleb, "fmm_order": fmm,
                    "precision": args.precision, "tol": args.tol, "options": extra},
         "roofline": roof(name, ms, nl, work),
         "roofline_top3": [roof(k, *v) for k, v in tops],
-        "energy": E, "iters": [st["iters_primal"], st["iters_adjoint"]],
+        "energy": E, "iters": [st["iters_primal"], st["iters_adjoint"]], "cap_pairs": st["n_cap_pairs"],
         "residuals": [st["resid_primal"], st["resid_adjoint"]],
         "phase_ms": {k: st[k] for k in ("ms_rhs", "ms_primal", "ms_adjoint", "ms_forces")},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])},
@@ -311,7 +334,7 @@ def main():
         log("oracle sample on the host")
         per = lambda *labels: sum(kt[k][1] for k in labels if k in kt) / args.steps
         n_c = per("sl_near", "sl_near_adjoint", "sl_field", "sl_adjoint")
-        n_ab = per("apply_LX", "apply_LTZ")
+        n_ab = per("apply_LX", "apply_LTZ", "near_lx", "near_ltz", "near_lx_f32", "near_ltz_f32")
         out["cpu_baseline"] = cpu_baseline(args, n_c, n_ab, atoms)
     print(json.dumps(out))
 

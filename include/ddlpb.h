@@ -183,9 +183,10 @@ void ddlpb_free(ddlpb_ctx* ctx);
  * for options that change the discrete problem: eta, precision, fmm_order).
  *   "eta"            switching width of chi_eta (Sec. 3.1), 0 < eta <= 1
  *   "precision"      0 = FP64 everywhere.
- *                    1 = mixed: the Jacobi sweeps of the preconditioner run the
- *                    near-field A/B kernels in FP32; flexible GMRES on the FP64
- *                    operator (FP64 residual, vectors, orthogonalisation, norms).
+ *                    1 = mixed: the preconditioner (the Krylov steps on L_AB and
+ *                    their Jacobi sweeps) runs the near-field A/B kernels in FP32;
+ *                    flexible GMRES on the FP64 operator (FP64 residual, vectors,
+ *                    orthogonalisation, norms) restores the tolerance.
  *                    2 = mixed with FP32 operator: FP64 iterative refinement (FP64
  *                    residual b - L x) around GMRES solves of the correction
  *                    equation in which the near-field kernels (operator and

@@ -1270,8 +1270,7 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
   VecOp jac = [&](const double* in, double* out) { precond(c, transpose, in, out); };
   if (c->pkrylov > 0 && c->pdelta < 0.0) {
     // Krylov preconditioner: pkrylov GMRES steps on L_AB (each preconditioned by the
-    // Jacobi sweeps, FP32 on the mixed path) in place of the sweeps alone; the outer
-    // method is flexible GMRES
+    // Jacobi sweeps) in place of the sweeps alone; the outer method is flexible GMRES
     VecOp opAB = [&](const double* in, double* out) {
       if (!transpose) {
         apply_LX(c, in, 1.0, in, -1.0, nullptr, nullptr, nullptr, 0.0, out);
@@ -1287,11 +1286,16 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
       precond(c, transpose, in, out);
       c->cur_prec = keep;
     };
+    // on the mixed path the whole inner solve (its L_AB products and sweeps) runs the
+    // near-field kernels in FP32; its vectors, dots and norms stay FP64
     VecOp inner = [&](const double* in, double* out) {
       int it = 0;
       double rr = 0;
+      const int keep = c->cur_prec;
+      if (fp32) c->cur_prec = 1;
       (void)gmres_core(c, opAB, jacp, in, out, 1e-30, c->pkrylov, c->pkrylov, 1, true, c->d_Vin, nullptr, c->d_t4,
                        c->d_t1, c->d_t5, &it, &rr);
+      c->cur_prec = keep;
       c->inner_total += it;
     };
     return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
