@@ -731,9 +731,18 @@ void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, co
     }
     if (lam) {
       KScope ks(c, "sl_adjoint_part", 4.0 * c->N * c->L * (double)c->M);
-      LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_lam_add<LMc>), dim3(c->M), dim3(128), (c->L + c->N) * sizeof(double),
-                                              c->stream, c->M, c->N, c->LY, c->d_Y, c->d_YT, c->d_leb, c->d_U, c->d_ycr,
-                                              c->d_yce, c->d_Cl, c->LUR, lam, llam, out));
+      // spheres per block: as many as fit 64 KB of LDS (at least one; 8 at 302 points)
+      const size_t per = (size_t)(c->L + c->N + 3 * c->L) * sizeof(double);
+      const int sb = (int)std::max<size_t>(1, std::min<size_t>(kLamSph, 65536 / per));
+      const size_t lds = per * sb;
+      LM_DISPATCH(c->lmax, {
+        if (lds > 65536)
+          HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lam_add<LMc>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((k_lam_add<LMc>), dim3((c->M + sb - 1) / sb), dim3(256), lds, c->stream, c->M, c->N,
+                           c->LY, sb, c->d_Y, c->d_YT, c->d_leb, c->d_U, c->d_ycr, c->d_yce, c->d_Cl, c->LUR, lam,
+                           llam, out);
+      });
       HIPCHK(hipGetLastError());
     }
     return;
