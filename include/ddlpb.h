@@ -208,6 +208,12 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "inner_iters"    inner GMRES steps on P per outer step (1..200, default 12)
  *   "max_iter"       maximal GMRES iterations per solve
  *   "theta"          FMM acceptance parameter (0 < theta < 1)
+ *   "leaf_size"      FMM leaf groups (1..64, default 1): a rejected pair of tree
+ *                    nodes of at most this many spheres each interacts sphere by
+ *                    sphere in the near field instead of being split further, which
+ *                    trades multipole-to-local translations for direct pairs; the
+ *                    expansions still start and end at the single spheres.  Set
+ *                    before the first solve (else ESTATE).
  *   "solver"         0 (default): GMRES as above; 1: the Jacobi-DIIS scheme of
  *                    Sec. 4, opening (macro-iterations X <- X + L_AB^-1 (g - L X) with DIIS,
  *                    L_AB^-1 by DIIS-accelerated Jacobi micro-iterations, both

@@ -126,6 +126,7 @@ struct ddlpb_ctx {
   double pdelta = -1.0;       // P keeps the single-layer blocks of spheres with |x_i-x_j| < r_i+r_j+pdelta
   bool warm_start = true;
   double theta = 0.6;
+  int leaf_size = 1;          // FMM leaf groups: nodes of at most this many spheres interact directly
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic, -1: block kernel)
   int m2l_lane = 1;           // order 12: the one-translation-per-lane M2L kernels (when m2l_waves is 0)
   int near_lane = 1;          // lmax <= 8: the near-field A/B kernels with one cap per lane
@@ -1903,7 +1904,7 @@ int ddlpb_setup(int32_t n_atoms, const double* centers, const double* radii, con
       if (fmm_order < lmax + 1) { delete c; return DDLPB_EINVAL; }
       fmm::build_tables(fmm_order, c->tables);
       fmm::build_tree(c->M, c->x.data(), c->r.data(), c->tree);
-      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree, c->leaf_size);
       c->stats.n_m2l = (int64_t)c->tree.m2l_src.size();
       c->stats.n_near_pairs = (int64_t)c->tree.near_idx.size();
     }
@@ -2301,12 +2302,21 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 2 && v <= 32)) return DDLPB_EINVAL;
     c->diis_max = (int)v;
+  } else if (k == "leaf_size") {
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v >= 1 && v <= 64 && v == (int)v)) return DDLPB_EINVAL;
+    c->leaf_size = (int)v;
+    if (c->fmm_order > 0) {
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree, c->leaf_size);
+      c->stats.n_m2l = (int64_t)c->tree.m2l_src.size();
+      c->stats.n_near_pairs = (int64_t)c->tree.near_idx.size();
+    }
   } else if (k == "theta") {
     if (fixed) return DDLPB_ESTATE;
     if (!(v > 0 && v < 1)) return DDLPB_EINVAL;
     c->theta = v;
     if (c->fmm_order > 0) {
-      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree, c->leaf_size);
       c->stats.n_m2l = (int64_t)c->tree.m2l_src.size();
       c->stats.n_near_pairs = (int64_t)c->tree.near_idx.size();
     }
@@ -2339,7 +2349,7 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
     if (c->fmm_order > 0) {
       // the leaves sit at the sphere centres: the tree and its lists follow the atoms
       fmm::build_tree(c->M, c->x.data(), c->r.data(), c->tree);
-      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree);
+      fmm::build_lists(c->M, c->r.data(), c->theta, c->tree, c->leaf_size);
     }
     if (c->dev_ready) {
       const bool relayout = c->nidx.size() > c->nnz_cap || c->pidx.size() > c->pnz_cap || c->cap_est > c->cap_cap ||

@@ -32,6 +32,8 @@ struct Tree {
   std::vector<int> level;         // [nnodes]
   std::vector<int> leaf_sphere;   // [nnodes], sphere index of a leaf or -1
   std::vector<int> sphere_leaf;   // [M], node index of the sphere's leaf
+  std::vector<int> sph;           // [M], spheres in tree order: node n holds sph[lo[n] .. hi[n])
+  std::vector<int> lo, hi;        // [nnodes]
   std::vector<int> level_ptr, level_nodes;  // nodes grouped by level (CSR)
   // interaction lists
   // per target node, source nodes (sorted); the lists are symmetric, so the list of a
@@ -45,6 +47,7 @@ inline void build_tree(int M, const double* x, const double* r, Tree& t) {
   std::vector<int> idx(M);
   std::iota(idx.begin(), idx.end(), 0);
   t.center.clear(); t.radius.clear(); t.child.clear(); t.parent.clear(); t.level.clear(); t.leaf_sphere.clear();
+  t.lo.clear(); t.hi.clear();
   t.sphere_leaf.assign(M, -1);
   std::function<int(int, int, int, int)> rec = [&](int lo, int hi, int par, int lev) -> int {
     const int id = (int)t.radius.size();
@@ -54,6 +57,8 @@ inline void build_tree(int M, const double* x, const double* r, Tree& t) {
     t.parent.push_back(par);
     t.level.push_back(lev);
     t.leaf_sphere.push_back(-1);
+    t.lo.push_back(lo);
+    t.hi.push_back(hi);
     double bmin[3] = {1e300, 1e300, 1e300}, bmax[3] = {-1e300, -1e300, -1e300};
     for (int k = lo; k < hi; ++k)
       for (int a = 0; a < 3; ++a) {
@@ -91,6 +96,7 @@ inline void build_tree(int M, const double* x, const double* r, Tree& t) {
     return id;
   };
   rec(0, M, -1, 0);
+  t.sph = idx;
   t.nnodes = (int)t.radius.size();
   t.nlevels = *std::max_element(t.level.begin(), t.level.end()) + 1;
   t.level_ptr.assign(t.nlevels + 1, 0);
@@ -142,18 +148,28 @@ inline void pairs_to_csr(const std::vector<std::vector<std::pair<int, int>>>& pa
 // Interaction lists by a symmetric dual traversal: self(A) = self(A1) + self(A2) +
 // mutual(A1, A2); mutual(A, B) is accepted as the two translations A -> B and B -> A
 // when R_A + R_B < theta |c_A - c_B|, is a near pair (both ways) when both are
-// leaves, and otherwise splits the larger node (ties by index).  The list of every
+// leaf groups -- nodes of at most leaf_size spheres, whose spheres then interact
+// directly pair by pair -- and otherwise splits the larger node (ties by index).
+// With leaf_size 1 the leaf groups are the single-sphere leaves.  The list of every
 // node is therefore also its transposed list.  The traversal is expanded
 // breadth-first into a frontier of pending tasks that host threads finish
 // depth-first; the lists are assembled by counting sorts with each list sorted, so
 // the result does not depend on the thread schedule.
-inline void build_lists(int M, const double* r, double theta, Tree& t) {
-  auto is_leaf = [&](int n) { return t.child[2 * n] < 0; };
+inline void build_lists(int M, const double* r, double theta, Tree& t, int leaf_size = 1) {
+  auto is_leaf = [&](int n) { return t.hi[n] - t.lo[n] <= leaf_size; };
+  // every sphere of A with every sphere of B (both orders when A != B)
+  auto all_pairs = [&](int A, int B, std::vector<std::pair<int, int>>& on) {
+    for (int a = t.lo[A]; a < t.hi[A]; ++a)
+      for (int b = t.lo[B]; b < t.hi[B]; ++b) {
+        on.push_back({t.sph[a], t.sph[b]});
+        if (A != B) on.push_back({t.sph[b], t.sph[a]});
+      }
+  };
   using Pairs = std::vector<std::pair<int, int>>;
   // one task (A == B: self, else mutual): emits pairs, appends subtasks to `sub`
   auto visit = [&](int A, int B, Pairs& om, Pairs& on, Pairs& sub) {
     if (A == B) {
-      if (is_leaf(A)) { on.push_back({t.leaf_sphere[A], t.leaf_sphere[A]}); return; }
+      if (is_leaf(A)) { all_pairs(A, A, on); return; }
       const int c1 = t.child[2 * A], c2 = t.child[2 * A + 1];
       sub.push_back({c1, c2});
       sub.push_back({c2, c2});
@@ -169,8 +185,7 @@ inline void build_lists(int M, const double* r, double theta, Tree& t) {
     }
     const bool la = is_leaf(A), lb = is_leaf(B);
     if (la && lb) {
-      on.push_back({t.leaf_sphere[A], t.leaf_sphere[B]});
-      on.push_back({t.leaf_sphere[B], t.leaf_sphere[A]});
+      all_pairs(A, B, on);
       return;
     }
     const bool split_a = lb || (!la && (t.radius[A] > t.radius[B] || (t.radius[A] == t.radius[B] && A < B)));

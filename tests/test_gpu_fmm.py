@@ -193,3 +193,28 @@ def test_m2l_lane_kernel_agrees(n, lmax):
     assert _rel(Y1, Y0) < 1e-12 and _rel(YT1, YT0) < 1e-12
     assert abs(E1 / E0 - 1) < 1e-10
     assert _rel(F1, F0) < 1e-8
+
+
+@pytest.mark.parametrize("leaf", [2, 4])
+def test_leaf_groups_match_direct(leaf):
+    """Leaf groups of several spheres (near field sphere by sphere inside rejected pairs
+    of groups) keep the FMM operator, its transpose and energy + forces at the accuracy
+    of single-sphere leaves against direct sums."""
+    x, r, q = inputs.lattice_cluster(700, seed=12)
+    L = 49
+    X = np.random.default_rng(8).normal(size=(2, 700, L))
+    d = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=0)
+    Yd, YTd = d.apply(X), d.apply(X, transpose=True)
+    Ed = d.solve(1e-10)
+    d.adjoint(1e-10)
+    Fd = d.forces()
+    f1 = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=12)
+    fk = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=12, options={"leaf_size": leaf})
+    assert fk.stats()["n_m2l"] < f1.stats()["n_m2l"] and fk.stats()["n_near_pairs"] > f1.stats()["n_near_pairs"]
+    e1 = max(_rel(f1.apply(X), Yd), _rel(f1.apply(X, transpose=True), YTd))
+    ek = max(_rel(fk.apply(X), Yd), _rel(fk.apply(X, transpose=True), YTd))
+    assert ek < max(2 * e1, 1e-9), (ek, e1)
+    E = fk.solve(1e-10)
+    fk.adjoint(1e-10)
+    assert abs(E / Ed - 1) < 1e-7
+    assert _rel(fk.forces(), Fd) < 1e-5
