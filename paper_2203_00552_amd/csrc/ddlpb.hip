@@ -135,6 +135,7 @@ struct ddlpb_ctx {
   int* d_f2r = nullptr;       // forward cap -> its position in the reverse lists
   double* d_capv = nullptr;   // (A, B) value pair of every reverse cap, [2 cap_cap]
   long* d_coff = nullptr;     // incore cache: first (padded) cap position of every sphere
+  int* d_jord = nullptr;      // spheres by decreasing number of reverse caps
   double* d_cache = nullptr;  // incore cache (owned by the context, outside the workspace)
   size_t cache_bytes = 0;
   int m2l_layout = 0;         // last M2L layout: wavefronts per block, negative with tables in global memory
@@ -426,6 +427,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_f2r = cv.take<int>(std::max<size_t>(c->cap_cap, 1));
   c->d_capv = cv.take<double>(2 * std::max<size_t>(c->cap_cap, 1));
   c->d_coff = cv.take<long>(M);
+  c->d_jord = cv.take<int>(M);
   c->d_pidx = cv.take<int>(std::max<size_t>(c->pnz_cap, 1));
   // dot-product scratch: the outer basis, the inner GMRES of either preconditioner and
   // the DIIS histories all call mdot with at most this many vectors
@@ -1698,6 +1700,7 @@ nearlane::NearArgs near_args(ddlpb_ctx* c) {
   a.isgr = c->d_isgr;
   a.cache = c->near_incore ? c->d_cache : nullptr;
   a.coff = c->d_coff;
+  a.jord = c->d_jord;
   return a;
 }
 
@@ -1716,6 +1719,13 @@ void setup_lane(ddlpb_ctx* c, const std::vector<int>& rcnt, long nrev) {
   HIPCHK(hipMemcpyAsync(&found, c->d_actcnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (found != c->ncap) return;  // forward and reverse lists disagree: keep the cap kernels
+  {
+    std::vector<int> ord(M);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) { return rcnt[p] > rcnt[q]; });
+    HIPCHK(hipMemcpyAsync(c->d_jord, ord.data(), M * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));  // ord is freed at the end of this block
+  }
   c->use_lane = true;
   if (!c->near_incore) return;
   // incore: sphere j's caps at padded position coff[j] (a multiple of 16)

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_ltz(NearArgs a, const double* __restric
   const int g = threadIdx.x & 15;
   const int jq = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4);
   const bool valid = jq < a.M;
-  const int j = valid ? jq : 0;  // idle groups still take part in the reductions
+  const int j = valid ? a.jord[jq] : 0;  // idle groups still take part in the reductions
   const int r0 = a.rptr[j], r1 = (valid && zr != nullptr) ? a.rptr[j + 1] : r0;
   const double xj = a.xyz[3 * j], yj = a.xyz[3 * j + 1], zj = a.xyz[3 * j + 2], rj = a.rad[j], irj = 1.0 / rj;
   const R kr2 = R(a.kappa * a.kappa * rj * rj);
@@ -377,11 +377,12 @@ __global__ __launch_bounds__(256) void k_lx(NearArgs a, const double* __restrict
   constexpr int L = (LM + 1) * (LM + 1), T = cache_stride(LM);
   __shared__ R sx[256 / kGroup][2 * L];
   const int g = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const int j = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4);
-  if (j < a.M)
+  const int jq = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+  const int j = jq < a.M ? a.jord[jq] : -1;
+  if (j >= 0)
     for (int t = g; t < 2 * L; t += kGroup) sx[grp][t] = R(X[(long)(t < L ? j : a.M + j) * L + (t < L ? t : t - L)]);
   __syncthreads();
-  if (j >= a.M) return;
+  if (j < 0) return;
   const int r0 = a.rptr[j], r1 = a.rptr[j + 1];
   const double xj = a.xyz[3 * j], yj = a.xyz[3 * j + 1], zj = a.xyz[3 * j + 2], rj = a.rad[j], irj = 1.0 / rj;
   const R kr2 = R(a.kappa * a.kappa * rj * rj);
@@ -442,8 +443,9 @@ template <int LM>
 __global__ __launch_bounds__(256) void k_fill(NearArgs a, double* __restrict__ cache) {
   constexpr int L = (LM + 1) * (LM + 1), T = cache_stride(LM);
   const int g = threadIdx.x & 15;
-  const int j = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4);
-  if (j >= a.M) return;
+  const int jq = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 4);
+  if (jq >= a.M) return;
+  const int j = a.jord[jq];
   const int r0 = a.rptr[j], r1 = a.rptr[j + 1];
   const double xj = a.xyz[3 * j], yj = a.xyz[3 * j + 1], zj = a.xyz[3 * j + 2], rj = a.rad[j], irj = 1.0 / rj;
   const double kr2 = a.kappa * a.kappa * rj * rj;

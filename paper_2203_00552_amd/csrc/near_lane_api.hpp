@@ -37,6 +37,8 @@ struct NearArgs {
   const int* rcn;      // reverse caps: point index n
   const double* rcw;   // reverse caps: omega_ij(x_i^n)
   const double* isgr;  // [M][LUR]: 1 / sigma_l(kappa^2 r_j^2)
+  const int* jord;     // [M]: spheres by decreasing number of reverse caps (work order:
+                       // the four spheres of a wavefront carry similar work)
   // incore cache (nullptr: everything on the fly).  Sphere j's caps start at cap
   // position coff[j] (a multiple of 16); the block of caps 16 b .. 16 b + 15 holds value
   // t of cap 16 b + q at cache[(16 b) * T + 16 t + q], T = cache_stride(lmax).
