@@ -233,6 +233,11 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "m2l_lane"       1 (default): at FMM order 12 the multipole-to-local
  *                    translations run one per lane (Appendix translation, unrolled
  *                    for order 12); 0: the wavefront kernel
+ *   "level_lane"     at FMM order 12 with the screened Coulomb kernel, the tree
+ *                    levels of at least this many nodes (default 1024) run their
+ *                    multipole-to-multipole and local-to-local translations one
+ *                    node per lane (same Appendix translation); smaller levels, and
+ *                    0, take the wavefront-per-node kernels
  *   "near_lane"      1 (default): for lmax <= 8 the near-field A/B couplings
  *                    (Sec. 2.2, A_ij and B_ij) run one neighbour cap per lane,
  *                    grouped by the sphere whose basis functions are evaluated;

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddlpb.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("ddlpb.hip", "near_lane.hip", "m2l_lane_yf.hip", "m2l_lane_yt.hip", "m2l_lane_lf.hip", "m2l_lane_lt.hip")]
+           ("ddlpb.hip", "near_lane.hip", "m2l_lane_yf.hip", "m2l_lane_yt.hip", "m2l_lane_lf.hip", "m2l_lane_lt.hip",
+            "level_lane_ym2m.hip", "level_lane_yl2l.hip", "level_lane_ym2mT.hip", "level_lane_yl2lT.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-pthread"]

@@ -129,6 +129,8 @@ struct ddlpb_ctx {
   int leaf_size = 1;          // FMM leaf groups: nodes of at most this many spheres interact directly
   int m2l_waves = 0;          // wavefronts per block of the LDS-resident M2L kernel (0: automatic, -1: block kernel)
   int m2l_lane = 1;           // order 12: the one-translation-per-lane M2L kernels (when m2l_waves is 0)
+  int level_lane = 1024;      // order 12, screened Coulomb: levels of at least this many nodes take the
+                              // one-translation-per-lane M2M / L2L kernels (0: never)
   int near_lane = 1;          // lmax <= 8: the near-field A/B kernels with one cap per lane
   int near_incore = 0;        // with near_lane: harmonics of every reverse cap kept in device memory
   bool use_lane = false;      // lane kernels set up for the current geometry
@@ -189,6 +191,7 @@ struct ddlpb_ctx {
   double* d_fjpad = nullptr;
   double* d_fZ[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [kernel][direction]
   int* d_fZslot[2] = {nullptr, nullptr};
+  double* d_fZl[2] = {nullptr, nullptr};  // level z-translation table [direction]
   int *d_fm2lord = nullptr, *d_fctr = nullptr;
   int *d_fJoff = nullptr, *d_fAoff = nullptr, *d_fchild = nullptr, *d_fparent = nullptr, *d_flevn = nullptr, *d_fm2lp = nullptr,
       *d_fm2ls = nullptr, *d_fnp = nullptr, *d_fni = nullptr,
@@ -473,6 +476,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
       for (int d = 0; d < 2; ++d) c->d_fZ[k][d] = cv.take<double>(std::max<size_t>(c->tables.Z[k][d].size(), 1));
       c->d_fZslot[k] = cv.take<int>(std::max<size_t>(c->tables.Zslot[k].size(), 1));
     }
+    for (int d = 0; d < 2; ++d) c->d_fZl[d] = cv.take<double>(std::max<size_t>(c->tables.Zlvl[d].size(), 1));
     c->d_fm2lord = cv.take<int>(nn);
     c->d_fctr = cv.take<int>(64);
     c->d_Mn = cv.take<double>(nn * P);
@@ -929,6 +933,10 @@ int lane_tables_ready(const fmm::Tables& tb) {
     HIPCHK(lane12::upload_yt(J.data(), JT.data()));
     HIPCHK(lane12::upload_lf(J.data(), JT.data()));
     HIPCHK(lane12::upload_lt(J.data(), JT.data()));
+    HIPCHK(lane12::upload_ym2m(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yl2l(J.data(), JT.data()));
+    HIPCHK(lane12::upload_ym2mT(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yl2lT(J.data(), JT.data()));
   }
   g_lane_state[dev] = state;
   return state;
@@ -1019,6 +1027,38 @@ void level_lds(ddlpb_ctx* c, const FmmDev& f, int& stage, size_t& bytes) {
   }
   (void)c;
 }
+// One level pass: which 0 M2M (upward), 1 L2L (downward), 2 transposed M2M (downward),
+// 3 transposed L2L (upward).  Order 12 with the screened Coulomb kernel takes the
+// one-node-per-lane kernels on levels of at least level_lane nodes; otherwise the
+// wavefront-per-node kernels run.
+void run_level(ddlpb_ctx* c, const FmmDev& f, int which, int lev, int stage, size_t lb, double* E) {
+  const auto& t = c->tree;
+  const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
+  const bool up = which == 0 || which == 3;
+  // translations: one per child of the level's nodes (upward), one per node (downward)
+  const double ntr = up ? (double)(t.level_ptr[lev + 2] - t.level_ptr[lev + 1]) : (double)cnt;
+  const int* nodes = c->d_flevn + t.level_ptr[lev];
+  if (f.kernel == 0 && f.p == lane12::kP && c->level_lane > 0 && cnt >= c->level_lane &&
+      (int)c->tables.Zlvl[0].size() == lane12::kZYn && lane_tables_ready(c->tables) > 0) {
+    KScope ks(c, "level_lane", flops_translation(f.p) * ntr);
+    hipError_t (*fn[4])(const FmmDev&, const double*, int, const int*, const int*, const int*, double*,
+                        hipStream_t) = {lane12::launch_ym2m, lane12::launch_yl2l, lane12::launch_ym2mT,
+                                        lane12::launch_yl2lT};
+    HIPCHK(fn[which](f, c->d_fZl[which >= 2 ? 1 : 0], cnt, nodes, c->d_fchild, c->d_fparent, E, c->stream));
+    return;
+  }
+  KScope ks(c, "level_generic", flops_translation(f.p) * ntr);
+  if (which == 0)
+    hipLaunchKernelGGL(k_fmm_upward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f, nodes, cnt,
+                       c->d_fchild, stage, E);
+  else if (which == 3)
+    hipLaunchKernelGGL(k_fmm_upward_T, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f, nodes, cnt,
+                       c->d_fchild, stage, E);
+  else
+    hipLaunchKernelGGL(k_fmm_downward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f, nodes, cnt,
+                       c->d_fparent, which == 2 ? 1 : 0, stage, E);
+  HIPCHK(hipGetLastError());
+}
 // sphere locals SL [M][P] of the far field of per-sphere sources src (degree ps, stride lds)
 void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, double* SL) {
   const auto& t = c->tree;
@@ -1030,17 +1070,9 @@ void fmm_forward(ddlpb_ctx* c, int kernel, const double* src, int ps, int lds, d
   KScope ks(c, kernel == 0 ? "pass_fmm_yukawa" : "pass_fmm_laplace",
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, ps, lds, c->d_sleaf, src, c->d_Mn);
-  for (int lev = t.nlevels - 2; lev >= 0; --lev) {
-    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_upward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
-                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fchild, stage, c->d_Mn);
-  }
+  for (int lev = t.nlevels - 2; lev >= 0; --lev) run_level(c, f, 0, lev, stage, lb, c->d_Mn);
   launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 0, c->d_Mn, c->d_Ln);
-  for (int lev = 1; lev < t.nlevels; ++lev) {
-    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_downward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
-                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fparent, 0, stage, c->d_Ln);
-  }
+  for (int lev = 1; lev < t.nlevels; ++lev) run_level(c, f, 1, lev, stage, lb, c->d_Ln);
   hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, c->d_Ln, 0, SL);
   HIPCHK(hipGetLastError());
 }
@@ -1056,17 +1088,9 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
             flops_translation(p) * (double)(t.m2l_src.size() + 2.0 * (t.nnodes - 1)));
   fill(c, c->d_Ln, (long)t.nnodes * P, 0.0);
   hipLaunchKernelGGL(k_fmm_leaf_set, dim3(c->M), dim3(64), 0, c->stream, c->M, p, p, P, c->d_sleaf, Lam, c->d_Ln);
-  for (int lev = t.nlevels - 2; lev >= 0; --lev) {
-    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_upward_T, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
-                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fchild, stage, c->d_Ln);
-  }
+  for (int lev = t.nlevels - 2; lev >= 0; --lev) run_level(c, f, 3, lev, stage, lb, c->d_Ln);
   launch_m2l(c, f, c->d_fm2lp, c->d_fm2ls, 1, c->d_Ln, c->d_Mn);  // symmetric lists: by source
-  for (int lev = 1; lev < t.nlevels; ++lev) {
-    const int cnt = t.level_ptr[lev + 1] - t.level_ptr[lev];
-    hipLaunchKernelGGL(k_fmm_downward, dim3(level_blocks(cnt)), dim3(64 * kLevelWaves), lb, c->stream, f,
-                       c->d_flevn + t.level_ptr[lev], cnt, c->d_fparent, 1, stage, c->d_Mn);
-  }
+  for (int lev = 1; lev < t.nlevels; ++lev) run_level(c, f, 2, lev, stage, lb, c->d_Mn);
   hipLaunchKernelGGL(k_fmm_leaf_get, dim3(c->M), dim3(64), 0, c->stream, c->M, p, pd, ldd, c->d_sleaf, c->d_Mn,
                      accumulate, out);
   HIPCHK(hipGetLastError());
@@ -1638,6 +1662,7 @@ void upload_and_init(ddlpb_ctx* c) {
       for (int d = 0; d < 2; ++d) up(c->d_fZ[k][d], c->tables.Z[k][d].data(), c->tables.Z[k][d].size() * sizeof(double));
       up(c->d_fZslot[k], c->tables.Zslot[k].data(), c->tables.Zslot[k].size() * sizeof(int));
     }
+    for (int d = 0; d < 2; ++d) up(c->d_fZl[d], c->tables.Zlvl[d].data(), c->tables.Zlvl[d].size() * sizeof(double));
     // sigma_l(kappa^2 r_i^2) up to degree p (normalisation of the sphere locals)
     std::vector<double> sgp((size_t)M * (p1 + 1)), sgt(p1 + 2), qs(M);
     for (int j = 0; j < M; ++j) {
@@ -2300,6 +2325,9 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "m2l_lane") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->m2l_lane = (int)v;
+  } else if (k == "level_lane") {
+    if (v < 0 || v > 1e9 || v != (double)(long)v) return DDLPB_EINVAL;
+    c->level_lane = (int)v;
   } else if (k == "near_lane" || k == "near_incore") {
     // cap structures depend on both: set before the first device call
     if (fixed) return DDLPB_ESTATE;

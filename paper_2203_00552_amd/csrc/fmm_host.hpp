@@ -283,6 +283,9 @@ struct Tables {
   // to the 64 lanes by longest-first balancing: Zslot[kern][2 s] = lo << 8 | |m| of
   // the pair in slot s (lane s mod 64; -1 when empty), Zslot[kern][2 s + 1] = offset.
   std::vector<double> Z[2][2];
+  // Yukawa z-translation coefficients without the (-1)^k sign, same layout as Z[0][dir],
+  // for the level passes (M2M, L2L), whose offsets are not sign-flipped
+  std::vector<double> Zlvl[2];
   std::vector<int> Zslot[2];
   int nslot = 0;
 };
@@ -326,6 +329,8 @@ inline void build_tables(int pmax, Tables& tb) {
       std::vector<int> off(npair);
       std::vector<double> work(npair);
       for (int d = 0; d < 2; ++d) tb.Z[kern][d].clear();
+      if (kern == 0)
+        for (int d = 0; d < 2; ++d) tb.Zlvl[d].clear();
       for (int lo = 0; lo <= pmax; ++lo)
         for (int am = 0; am <= lo; ++am) {
           const int u = lo * (lo + 1) / 2 + am;
@@ -336,8 +341,10 @@ inline void build_tables(int pmax, Tables& tb) {
             for (int d = 0; d < 2; ++d) {
               const int l = d ? lo : li, lp = d ? li : lo;
               if (kern == 0) {  // (-1)^k folded in: the kernel sums against k_n(z) z^n
-                for (int k = am; k <= kmax; ++k)
+                for (int k = am; k <= kmax; ++k) {
                   tb.Z[kern][d].push_back(tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k] * ((k & 1) ? -1.0 : 1.0));
+                  tb.Zlvl[d].push_back(tb.A[(((size_t)l * P1 + lp) * P1 + am) * P1 + k]);
+                }
               } else {
                 tb.Z[kern][d].push_back(tb.AL[1 * (size_t)P1 * P1 * P1 + ((size_t)l * P1 + lp) * P1 + am]);
               }

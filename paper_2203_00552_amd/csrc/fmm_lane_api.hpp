@@ -78,5 +78,19 @@ DDLPB_M2L_LANE_DECL(lf)
 DDLPB_M2L_LANE_DECL(lt)
 #undef DDLPB_M2L_LANE_DECL
 
+// Level translations of the screened Coulomb expansions (fmm_lane_level.hpp), one node
+// of the level per lane: ym2m (upward pass), yl2l (downward pass) and their transposes
+// ym2mT (transposed downward pass), yl2lT (transposed upward pass).  Z is the
+// z-translation table of the level kinds in the direction of the instance.
+#define DDLPB_LEVEL_LANE_DECL(NAME)                                                                      \
+  hipError_t upload_##NAME(const double* J, const double* JT);                                          \
+  hipError_t launch_##NAME(const FmmDev& f, const double* Z, int count, const int* nodes, const int* child, \
+                           const int* parent, double* E, hipStream_t s);
+DDLPB_LEVEL_LANE_DECL(ym2m)
+DDLPB_LEVEL_LANE_DECL(yl2l)
+DDLPB_LEVEL_LANE_DECL(ym2mT)
+DDLPB_LEVEL_LANE_DECL(yl2lT)
+#undef DDLPB_LEVEL_LANE_DECL
+
 }  // namespace lane12
 }  // namespace ddlpb

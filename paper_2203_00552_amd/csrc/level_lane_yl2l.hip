@@ -1,0 +1,4 @@
+// Level translations of order 12, one per lane (screened Coulomb, local-to-local).
+#include "fmm_lane_level.hpp"
+
+DDLPB_LEVEL_LANE_INSTANCE(yl2l, 2, false)

@@ -218,3 +218,27 @@ def test_leaf_groups_match_direct(leaf):
     fk.adjoint(1e-10)
     assert abs(E / Ed - 1) < 1e-7
     assert _rel(fk.forces(), Fd) < 1e-5
+
+
+@pytest.mark.parametrize("n,thresh", [(400, 1), (3000, 1), (3000, 200)])
+def test_level_lane_kernels_agree(n, thresh):
+    """Order 12, screened Coulomb: the one-node-per-lane multipole-to-multipole and
+    local-to-local kernels (every level, or only the levels of at least `thresh` nodes)
+    give the operator, its transpose, the energy and the forces of the wavefront
+    kernels to rounding."""
+    x, r, q = inputs.lattice_cluster(n, seed=21)
+    L = 49
+    X = np.random.default_rng(4).normal(size=(2, n, L))
+    res = []
+    for lvl in (thresh, 0):
+        f = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=12, options={"level_lane": lvl, "kernel_timing": 1})
+        Y, YT = f.apply(X), f.apply(X, transpose=True)
+        E = f.solve(1e-10)
+        f.adjoint(1e-10)
+        res.append((Y, YT, E, f.forces()))
+        assert ("level_lane" in f.kernel_times()) == (lvl > 0)
+        f.close()
+    (Y1, YT1, E1, F1), (Y0, YT0, E0, F0) = res
+    assert _rel(Y1, Y0) < 1e-12 and _rel(YT1, YT0) < 1e-12, (_rel(Y1, Y0), _rel(YT1, YT0))
+    assert abs(E1 / E0 - 1) < 1e-10
+    assert _rel(F1, F0) < 1e-8
