@@ -257,13 +257,22 @@ class Problem:
         return out
 
     def energy_complex_step(self, atom, coord, h=1e-30):
-        """dE/dx_{atom,coord} by the complex step Im E(x + i h e)/h (dense path)."""
+        """dE/dx_{atom,coord} by the complex step Im E(x + i h e)/h (dense path);
+        coord 3 gives dE/dr_atom (the radius with every radial constant of Sec. 2.2 that
+        depends on it: r^-l, i_l(kappa r), k_l(kappa r), i_l'/i_l, C_l)."""
         d = ctypes.c_double(0.0)
         rc = _load().oracle_energy_cs(*self._args(), ctypes.c_int(atom), ctypes.c_int(coord),
                                       ctypes.c_double(h), ctypes.byref(d))
         if rc != 0:
             raise RuntimeError("complex-step solve failed")
         return d.value
+
+
+    def radius_gradient(self, atoms=None, h=1e-30):
+        """dE/dr_j for the listed atoms (all by default) by complex steps of the dense
+        solve (Sec. 3: the energy as a function of any parameter of the model)."""
+        atoms = range(self.M) if atoms is None else atoms
+        return np.array([self.energy_complex_step(a, 3, h) for a in atoms])
 
 
 # ------------------------------------------------------------ table routines

@@ -146,8 +146,9 @@ T sigma_l(int l, const T& z2) {
   return sum;
 }
 
-// i_l(z) for real z > 0.
-double sph_i(int l, double z) { return std::pow(z, l) * sigma_l<double>(l, z * z); }
+// i_l(z) for z > 0 (real, or complex with a tiny imaginary part for complex steps).
+template <class T>
+T sph_i(int l, const T& z) { return std::pow(z, l) * sigma_l<T>(l, z * z); }
 
 // k_l(z) = sqrt(pi/(2z)) K_{l+1/2}(z), l = 0..lmax, by the stable upward
 // recurrence k_{l+1} = k_{l-1} + (2l+1)/z k_l.
@@ -158,14 +159,17 @@ void sph_k_all(int lmax, const T& z, T* k) {
   if (lmax >= 1) k[1] = (PI / 2.0) * e * (z + 1.0) / (z * z);
   for (int l = 1; l + 1 <= lmax; ++l) k[l + 1] = k[l - 1] + (2.0 * l + 1.0) / z * k[l];
 }
-double sph_k(int l, double z) {
-  std::vector<double> k(l + 2);
-  sph_k_all<double>(l + 1, z, k.data());
+template <class T>
+T sph_k(int l, const T& z) {
+  std::vector<T> k(l + 2);
+  sph_k_all<T>(l + 1, z, k.data());
   return k[l];
 }
 // Derivatives (d/dz):  i_l' = i_{l+1} + (l/z) i_l,   k_l' = -k_{l+1} + (l/z) k_l.
-double sph_i_prime(int l, double z) { return sph_i(l + 1, z) + l / z * sph_i(l, z); }
-double sph_k_prime(int l, double z) { return -sph_k(l + 1, z) + l / z * sph_k(l, z); }
+template <class T>
+T sph_i_prime(int l, const T& z) { return sph_i(l + 1, z) + double(l) / z * sph_i(l, z); }
+template <class T>
+T sph_k_prime(int l, const T& z) { return T(0.0) - sph_k(l + 1, z) + double(l) / z * sph_k(l, z); }
 
 // ------------------------------------------------------ switching function
 // p_eta(t) = eta^-5 (1-t)^3 (6 t^2 + (15 eta - 12) t + 10 eta^2 - 15 eta + 6)
@@ -190,13 +194,14 @@ template <class T>
 struct Problem {
   int M, lmax, L, N;
   std::vector<T> x;             // [M][3] centres
-  std::vector<double> r, q;     // radii, charges
+  std::vector<T> r;             // radii (complex for complex-step derivatives in r)
+  std::vector<double> q;        // charges
   double eps1, eps2, kappa, eta;
   std::vector<double> s, w;     // Lebedev points [N][3], weights [N]
   std::vector<double> Y;        // Y_lm(s_n)  [N][L]
-  std::vector<double> Cl, Dl;   // C_l^j, i_l'(r_j)/i_l(r_j)  [M][lmax+1]
-  std::vector<double> sig_r;    // sigma_l(kappa^2 r_j^2)     [M][lmax+1]
-  std::vector<double> k_r;      // k_l(kappa r_j)             [M][lmax+1]
+  std::vector<T> Cl, Dl;        // C_l^j, i_l'(r_j)/i_l(r_j)  [M][lmax+1]
+  std::vector<T> sig_r;         // sigma_l(kappa^2 r_j^2)     [M][lmax+1]
+  std::vector<T> k_r;           // k_l(kappa r_j)             [M][lmax+1]
   std::vector<std::vector<int>> nbr;  // N_i
   // grid fields
   std::vector<T> xg;            // grid points x_i^n [M][N][3]
@@ -207,25 +212,30 @@ struct Problem {
     M = M_; lmax = lmax_; L = (lmax + 1) * (lmax + 1); N = N_;
     x.resize(3 * M);
     for (int k = 0; k < 3 * M; ++k) x[k] = T(x_[k]);
-    r.assign(r_, r_ + M);
+    r.resize(M);
+    for (int k = 0; k < M; ++k) r[k] = T(r_[k]);
     q.assign(q_, q_ + M);
     eps1 = e1; eps2 = e2; kappa = kap; eta = et;
     s.assign(s_, s_ + 3 * N);
     w.assign(w_, w_ + N);
     Y.resize((size_t)N * L);
     for (int n = 0; n < N; ++n) sph_harm_unit(lmax, &s[3 * n], &Y[(size_t)n * L]);
+    radial_constants();
+  }
+  // per-sphere constants of the radii (Sec. 2.2): C_l^j, i_l'/i_l, sigma_l and k_l at r_j
+  void radial_constants() {
     Cl.resize((size_t)M * (lmax + 1));
     Dl.resize((size_t)M * (lmax + 1));
     sig_r.resize((size_t)M * (lmax + 1));
     k_r.resize((size_t)M * (lmax + 1));
     for (int j = 0; j < M; ++j) {
-      double z = kappa * r[j];
+      T z = kappa * r[j];
       for (int l = 0; l <= lmax; ++l) {
-        double di = kappa * sph_i_prime(l, z) / sph_i(l, z);   // i_l'(r_j)/i_l(r_j), d/dr
-        double dk = kappa * sph_k_prime(l, z) / sph_k(l, z);   // k_l'(r_j)/k_l(r_j), d/dr
+        T di = kappa * sph_i_prime(l, z) / sph_i(l, z);   // i_l'(r_j)/i_l(r_j), d/dr
+        T dk = kappa * sph_k_prime(l, z) / sph_k(l, z);   // k_l'(r_j)/k_l(r_j), d/dr
         Cl[j * (lmax + 1) + l] = 1.0 / (di - dk);
         Dl[j * (lmax + 1) + l] = di;
-        sig_r[j * (lmax + 1) + l] = sigma_l<double>(l, z * z);
+        sig_r[j * (lmax + 1) + l] = sigma_l<T>(l, z * z);
         k_r[j * (lmax + 1) + l] = sph_k(l, z);
       }
     }
@@ -239,7 +249,7 @@ struct Problem {
         if (i == j) continue;
         double d2 = 0;
         for (int a = 0; a < 3; ++a) { double dd = re(x[3 * i + a]) - re(x[3 * j + a]); d2 += dd * dd; }
-        if (std::sqrt(d2) < r[i] + r[j]) nbr[i].push_back(j);
+        if (std::sqrt(d2) < re(r[i]) + re(r[j])) nbr[i].push_back(j);
       }
   }
 
@@ -279,7 +289,7 @@ struct Problem {
     for (int a = 0; a < 3; ++a) v[a] = p[a] - S_(re_or(x[3 * j + a]));
     solid_harmonics<S_>(lmax, v[0], v[1], v[2], out);
     for (int l = 0; l <= lmax; ++l) {
-      double sc = std::pow(r[j], -l);
+      T sc = std::pow(r[j], -l);
       for (int m = -l; m <= l; ++m) out[lm_index(l, m)] = out[lm_index(l, m)] * sc;
     }
   }
@@ -513,8 +523,8 @@ struct Problem {
       }
       for (int lm = 0; lm < L; ++lm) {
         int l = lof(lm);
-        double a = (eps1 / eps2) * (double(l) / r[j]);
-        double bb = -Dl[j * (lmax + 1) + l];
+        T a = (eps1 / eps2) * (double(l) / r[j]);
+        T bb = T(0.0) - Dl[j * (lmax + 1) + l];
         const double sAB = part == 2 ? 0.0 : 1.0;
         W[(size_t)j * L + lm] = sAB * (Zr[(size_t)j * L + lm] - accA[lm]) + a * mu[lm];
         W[(size_t)(M + j) * L + lm] = sAB * (Ze[(size_t)j * L + lm] - accB[lm]) + bb * mu[lm];
@@ -1134,7 +1144,12 @@ void oracle_forces_from(ORACLE_ARGS, const double* X, const double* Xa, double* 
 int oracle_energy_cs(ORACLE_ARGS, int atom, int coord, double h, double* dE) {
   Problem<cplx> P;
   P.init(M, x, r, q, eps1, eps2, kappa, eta, lmax, N, s, w);
-  P.x[3 * atom + coord] += cplx(0.0, h);
+  if (coord < 3) {
+    P.x[3 * atom + coord] += cplx(0.0, h);
+  } else {  // coord 3: the radius r_atom (every radial constant follows it)
+    P.r[atom] += cplx(0.0, h);
+    P.radial_constants();
+  }
   P.build_neighbours();
   P.build_grid();
   std::vector<cplx> Lm, g;

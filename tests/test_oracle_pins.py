@@ -505,3 +505,62 @@ def test_dielectric_gradient_euler_identity():
     E = P.solve("dense", forces=False)["energy"]
     assert abs((P.eps1 * g[0] + P.eps2 * g[1]) / -E - 1) < 1e-9
     assert g[0] > 0 and g[1] < 0
+
+
+# ------------------------------------------------------------ radius gradient
+@pytest.mark.parametrize("a,q,e1,e2,kap", [(1.7, 0.8, 1.0, 78.54, 0.104), (2.3, -1.2, 2.0, 40.0, 0.5)])
+def test_radius_gradient_single_sphere_closed_form(a, q, e1, e2, kap):
+    """E(a) = q^2/(2a) (1/(eps_out (1 + kappa a)) - 1/eps_in) for one sphere with a centred
+    charge, so dE/da = -E/a - q^2 kappa / (2 a eps_out (1 + kappa a)^2)."""
+    P = oracle.Problem([[0.3, 0.1, -0.2]], [a], [q], e1, e2, kap, lmax=4, n_lebedev=110)
+    E = q * q / (2 * a) * (1 / (e2 * (1 + kap * a)) - 1 / e1)
+    ref = -E / a - q * q * kap / (2 * a * e2 * (1 + kap * a) ** 2)
+    assert abs(P.radius_gradient()[0] / ref - 1) < 1e-11
+
+
+def test_radius_gradient_central_difference():
+    """The complex step in r_j equals Richardson-extrapolated central differences of the
+    real solve (fourth order, h = 2e-4 A) on an overlapping cluster, where r_j also
+    moves the switching regions of the neighbours."""
+    x, r, q = inputs.small_cluster(2)
+    args = dict(lmax=6, n_lebedev=110)
+    P = oracle.Problem(x, r, q, **args)
+    atoms = [0, 3, 7, 10]
+    g = P.radius_gradient(atoms)
+
+    def energy(k, d):
+        rr = r.copy()
+        rr[k] += d
+        return oracle.Problem(x, rr, q, **args).solve("dense", forces=False)["energy"]
+
+    h = 2e-4
+    for a, ga in zip(atoms, g):
+        d1 = (energy(a, h) - energy(a, -h)) / (2 * h)
+        d2 = (energy(a, 2 * h) - energy(a, -2 * h)) / (4 * h)
+        fd = (4 * d1 - d2) / 3
+        assert abs(fd - ga) < 1e-7 * np.abs(g).max(), (a, fd, ga)
+
+
+def test_radius_gradient_scaling_identity():
+    """Scaling every length by s and kappa by 1/s scales the energy by 1/s (eps fixed), so
+    sum_j (x_j . grad_j E + r_j dE/dr_j) - kappa dE/dkappa = -E.  Positions enter through
+    the adjoint forces, radii through the complex steps in r, kappa through central
+    differences."""
+    x, r, q = inputs.small_cluster(3)
+    args = dict(lmax=6, n_lebedev=110)
+    kap = 0.2
+    P = oracle.Problem(x, r, q, 1.0, 78.54, kap, **args)
+    res = P.solve("dense")
+    E, F = res["energy"], res["forces"]
+    gr = P.radius_gradient()
+
+    def energy(k):
+        return oracle.Problem(x, r, q, 1.0, 78.54, k, **args).solve("dense", forces=False)["energy"]
+
+    h = 1e-4 * kap
+    d1 = (energy(kap + h) - energy(kap - h)) / (2 * h)
+    d2 = (energy(kap + 2 * h) - energy(kap - 2 * h)) / (4 * h)
+    dk = (4 * d1 - d2) / 3
+    lhs = -(x * F).sum() + (r * gr).sum() - kap * dk
+    assert abs(lhs / -E - 1) < 1e-8, (lhs, -E)
+    assert np.abs(r * gr).sum() > 0.1 * abs(E)
