@@ -175,6 +175,19 @@ int ddlpb_charge_gradient(ddlpb_ctx* ctx, double* dedq_out);
  */
 int ddlpb_dielectric_gradient(ddlpb_ctx* ctx, double* dedeps_out);
 
+/*
+ * ddlpb_radius_gradient -- dE_s/dr_j for every atom, written to dedr_out [M] (host,
+ * e^2/Angstrom^2), from the same adjoint solution (Sec. 3: dE/d lambda =
+ * 1/2 <X_adj, dg/d lambda - (dL/d lambda) X> for any parameter lambda).  The radius
+ * moves the sphere's grid points radially (x_j^n = x_j + r_j s_n), enters the
+ * switching function through |x - x_j| / r_j (Sec. 3.1) and every per-degree
+ * normaliser of the sphere's bases and constants (Sec. 2.2: r_j^-l, i_l(kappa r_j),
+ * k_l(kappa r_j), C_l^j and the y terms of C1 and C2).  The force intermediates are
+ * recomputed (one more far-field pass of each kind with the FMM).  Requires a prior
+ * ddlpb_adjoint (else ESTATE).  Errors: EINVAL, ESTATE, EDEVICE.
+ */
+int ddlpb_radius_gradient(ddlpb_ctx* ctx, double* dedr_out);
+
 /* ddlpb_free -- release the context and any device memory it allocated. NULL is a no-op. */
 void ddlpb_free(ddlpb_ctx* ctx);
 

@@ -19,7 +19,7 @@ EXPORTS = ["ddlpb_setup", "ddlpb_solve", "ddlpb_adjoint", "ddlpb_forces", "ddlpb
            "ddlpb_get_stats", "ddlpb_strerror", "ddlpb_get_grid", "ddlpb_get_solution", "ddlpb_get_rhs",
            "ddlpb_apply", "ddlpb_kernel_times", "ddlpb_kernel_times_reset", "ddlpb_charge_gradient",
            "ddlpb_eval_potentials", "ddlpb_eval_potentials_noalloc",
-           "ddlpb_dielectric_gradient"]
+           "ddlpb_dielectric_gradient", "ddlpb_radius_gradient"]
 
 
 class DDLPBError(RuntimeError):
@@ -67,6 +67,7 @@ def load():
         lib.ddlpb_forces.argtypes = [c_void_p, _dp]
         lib.ddlpb_charge_gradient.argtypes = [c_void_p, _dp]
         lib.ddlpb_dielectric_gradient.argtypes = [c_void_p, _dp]
+        lib.ddlpb_radius_gradient.argtypes = [c_void_p, _dp]
         lib.ddlpb_eval_potentials.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
         lib.ddlpb_eval_potentials_noalloc.argtypes = [c_void_p, c_int, _dp, ctypes.POINTER(ctypes.c_int32), _dp]
         lib.ddlpb_free.argtypes = [c_void_p]
@@ -198,6 +199,12 @@ class Context:
         out = np.zeros(2)
         check(load().ddlpb_dielectric_gradient(self._h, ptr(out)), "ddlpb_dielectric_gradient")
         return out
+
+    def radius_gradient(self):
+        """dE/dr_j [M] from the adjoint solution (needs a prior adjoint)."""
+        g = np.zeros(self.M)
+        check(load().ddlpb_radius_gradient(self._h, ptr(g)), "ddlpb_radius_gradient")
+        return g
 
     def update_centers(self, centers):
         x = np.ascontiguousarray(centers, dtype=np.float64).reshape(self.M, 3)

@@ -161,6 +161,7 @@ struct ddlpb_ctx {
   int *d_actcnt = nullptr, *d_actptr = nullptr, *d_actsph = nullptr, *d_actn = nullptr;
   double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_kr = nullptr;
   double *d_dtab = nullptr;
+  double *d_rtab = nullptr;  // radius derivatives of the radial constants [4][M][LUR]
   double *d_m = nullptr, *d_lam = nullptr;
   double *d_psi = nullptr, *d_e = nullptr, *d_Phi = nullptr, *d_h = nullptr, *d_zr = nullptr, *d_ze = nullptr,
          *d_cg = nullptr, *d_eta = nullptr, *d_xr = nullptr, *d_xe = nullptr;
@@ -385,6 +386,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_ur = cv.take<double>(M * c->LUR);
   c->d_kr = cv.take<double>(M * c->LUR);
   c->d_dtab = cv.take<double>(3 * (size_t)c->L * c->LP);
+  c->d_rtab = cv.take<double>(4 * (size_t)M * c->LUR);
   c->d_m = cv.take<double>(M * c->L);
   c->d_lam = cv.take<double>(M * c->LP);
   c->d_psi = cv.take<double>(MN);
@@ -1587,7 +1589,7 @@ void upload_and_init(ddlpb_ctx* c) {
   const int M = c->M, N = c->N, LUR = c->LUR;
   // per-sphere radial tables (FP64, host)
   std::vector<double> ycr((size_t)M * LUR), yce((size_t)M * LUR), Cl((size_t)M * LUR), sgr((size_t)M * LUR),
-      ur((size_t)M * LUR), kr((size_t)M * LUR);
+      ur((size_t)M * LUR), kr((size_t)M * LUR), rtab(4 * (size_t)M * LUR, 0.0);
   std::vector<double> sg(LUR + 1), kk(LUR + 1);
   double rmax = 0;
   for (int j = 0; j < M; ++j) {
@@ -1604,6 +1606,17 @@ void upload_and_init(ddlpb_ctx* c) {
       sgr[(size_t)j * LUR + l] = sg[l];
       ur[(size_t)j * LUR + l] = kk[l] / std::pow(rj, l);
       kr[(size_t)j * LUR + l] = kk[l];
+      if (l + 1 < LUR) {
+        // radius derivatives (dE/dr_j): dk_l = kappa k_l'/k_l, C_l'/C_l = 2/r + D_l + dk_l,
+        // (eps1/eps2) l/r^2, D_l' = kappa^2 + l(l+1)/r^2 - 2 D_l/r - D_l^2 (Bessel equation)
+        const double Dl = c->kappa * c->kappa * rj * sg[l + 1] / sg[l] + l / rj;
+        const double dk = -c->kappa * kk[l + 1] / kk[l] + l / rj;
+        const size_t jl = (size_t)j * LUR + l, MU = (size_t)M * LUR;
+        rtab[jl] = dk;
+        rtab[MU + jl] = 2.0 / rj + Dl + dk;
+        rtab[2 * MU + jl] = (c->eps1 / c->eps2) * l / (rj * rj);
+        rtab[3 * MU + jl] = c->kappa * c->kappa + l * (l + 1.0) / (rj * rj) - 2.0 * Dl / rj - Dl * Dl;
+      }
     }
   }
   c->nterms = host::sigma_terms(c->lmax, c->kappa * c->kappa * rmax * rmax);
@@ -1642,6 +1655,7 @@ void upload_and_init(ddlpb_ctx* c) {
   up(c->d_yce, yce.data(), yce.size() * sizeof(double));
   up(c->d_Cl, Cl.data(), Cl.size() * sizeof(double));
   up(c->d_sgr, sgr.data(), sgr.size() * sizeof(double));
+  up(c->d_rtab, rtab.data(), rtab.size() * sizeof(double));
   std::vector<double> isgr(sgr.size());
   for (size_t k = 0; k < sgr.size(); ++k) isgr[k] = sgr[k] != 0.0 ? 1.0 / sgr[k] : 0.0;
   up(c->d_isgr, isgr.data(), isgr.size() * sizeof(double));
@@ -1888,6 +1902,59 @@ void compute_rhs(ddlpb_ctx* c) {
   c->rhs_ready = true;
 }
 
+// Fields of the frozen functional E_f shared by the forces and the radius gradient
+// (Sec. 3): xi = Syn(X_adj) on the grids, grid charges c = w U xi_s, h = e + Syn(y(X)),
+// m = C (.) An(U h), Phi = Phi[m], lambda' (other spheres, degree lmax+1), eta =
+// Syn(C (.) lambda), the gradient of Phi' at the active points and the target-side point
+// gradients fpt (psi_0, d_n psi_0 of the other charges and the single-layer field of
+// the other spheres).
+void adjoint_fields(ddlpb_ctx* c) {
+  const int M = c->M, N = c->N;
+  syn2(c, c->d_Xa, 0, c->d_xr, c->d_xe);
+  syn2(c, c->d_Xa, 1, c->d_cg, nullptr);
+  moments(c, c->d_X, c->d_e, c->d_h, c->d_m);
+  sl_field_full(c, c->d_m, c->d_Phi);
+  sl_adjoint_full(c, c->d_cg, c->lmax + 1, 1, c->LP, c->d_lam);
+  LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eta<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->LY, c->d_Y,
+                                          c->d_cg, c->d_lam, c->LP, c->d_Cl, c->LUR, c->d_eta));
+  HIPCHK(hipGetLastError());
+  if (c->nact == 0) return;
+  const bool fmmode = c->fmm_order > 0;
+  // grad Phi' at active points (near part by pairs, far part from the sphere locals)
+  if (!fmmode) {
+    sl_field(c, c->d_m, true, 1, c->d_gphi);
+  } else {
+    KScope ks(c, "sl_near_grad", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
+                                            c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
+                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_ur, c->LUR,
+                                            c->kappa, 1, 0, c->d_gphi));
+    HIPCHK(hipGetLastError());
+  }
+  if (fmmode) {
+    fmm_forward(c, 0, c->d_m, c->lmax, c->L, c->d_SL);
+    P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_grad_yuk<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
+                                                c->stream, c->nact, c->d_actsph, c->d_actn, c->d_rad, c->d_leb,
+                                                c->d_sgp, c->fmm_order + 2, c->kappa, c->nterms_p, c->d_SL,
+                                                c->d_gphi));
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_force_points, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, M, N, c->nact, c->d_actsph,
+                     c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_xe,
+                     c->d_eta, c->d_gphi, fmmode ? 0 : 1, c->d_fpt);
+  HIPCHK(hipGetLastError());
+  if (fmmode) {
+    hipLaunchKernelGGL(k_force_points_lap_list, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, N, c->nact,
+                       c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U,
+                       c->d_xr, c->d_eta, c->d_fnp, c->d_fni, c->d_fpt);
+    fmm_forward(c, 1, c->d_qsrc, 0, 1, c->d_SL);
+    P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_force_lap<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
+                                                c->stream, N, c->nact, c->d_actsph, c->d_actn, c->d_rad, c->d_leb,
+                                                c->d_U, c->d_xr, c->d_eta, c->eps1, c->eps2, c->d_SL, c->d_fpt));
+    HIPCHK(hipGetLastError());
+  }
+}
+
 double elapsed_ms(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -2005,40 +2072,8 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
   return guarded([&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
     const int M = c->M, N = c->N;
-    const long MN = (long)M * N;
-    // xi_r, xi_e on the grid; grid charges c = w U xi_s
-    syn2(c, c->d_Xa, 0, c->d_xr, c->d_xe);
-    syn2(c, c->d_Xa, 1, c->d_cg, nullptr);
-    // h = e + Syn(y(X)), m = C (.) An(U h), Phi = Phi[m] (full)
-    moments(c, c->d_X, c->d_e, c->d_h, c->d_m);
-    sl_field_full(c, c->d_m, c->d_Phi);
-    // lambda' (other spheres only, degree lmax+1) and eta = Syn(C (.) lambda)
-    sl_adjoint_full(c, c->d_cg, c->lmax + 1, 1, c->LP, c->d_lam);
-    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_eta<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->LY, c->d_Y,
-                                            c->d_cg, c->d_lam, c->LP, c->d_Cl, c->LUR, c->d_eta));
-    HIPCHK(hipGetLastError());
+    adjoint_fields(c);
     const bool fmmode = c->fmm_order > 0;
-    // grad Phi' at active points (near part by pairs, far part from the sphere locals)
-    if (c->nact > 0) {
-      if (!fmmode) {
-        sl_field(c, c->d_m, true, 1, c->d_gphi);
-      } else {
-        KScope ks(c, "sl_near_grad", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
-        LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
-                                                c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
-                                                c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_ur, c->LUR,
-                                                c->kappa, 1, 0, c->d_gphi));
-        HIPCHK(hipGetLastError());
-      }
-      if (fmmode) {
-        fmm_forward(c, 0, c->d_m, c->lmax, c->L, c->d_SL);
-        P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_grad_yuk<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
-                                                    c->stream, c->nact, c->d_actsph, c->d_actn, c->d_rad, c->d_leb,
-                                                    c->d_sgp, c->fmm_order + 2, c->kappa, c->nterms_p, c->d_SL,
-                                                    c->d_gphi));
-        HIPCHK(hipGetLastError());
-      }
-    }
     // switching / near-field terms
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_force_switch<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->d_leb,
                                             c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U, c->d_sgr,
@@ -2048,21 +2083,6 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
     // target-side point terms, summed per sphere
     fill(c, c->d_fpts, 3L * M, 0.0);
     if (c->nact > 0) {
-      hipLaunchKernelGGL(k_force_points, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, M, N, c->nact,
-                         c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U,
-                         c->d_xr, c->d_xe, c->d_eta, c->d_gphi, fmmode ? 0 : 1, c->d_fpt);
-      HIPCHK(hipGetLastError());
-      if (fmmode) {
-        hipLaunchKernelGGL(k_force_points_lap_list, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, N, c->nact,
-                           c->d_actsph, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U,
-                           c->d_xr, c->d_eta, c->d_fnp, c->d_fni, c->d_fpt);
-        fmm_forward(c, 1, c->d_qsrc, 0, 1, c->d_SL);
-        P_DISPATCH(c->fmm_order, hipLaunchKernelGGL((k_local_force_lap<PDc>), dim3(nblk(c->nact, 128)), dim3(128), 0,
-                                                    c->stream, N, c->nact, c->d_actsph, c->d_actn, c->d_rad,
-                                                    c->d_leb, c->d_U, c->d_xr, c->d_eta, c->eps1, c->eps2, c->d_SL,
-                                                    c->d_fpt));
-        HIPCHK(hipGetLastError());
-      }
       hipLaunchKernelGGL(k_sum_points, dim3(M), dim3(256), 0, c->stream, M, c->d_actptr, c->d_fpt, c->d_fpts);
       HIPCHK(hipGetLastError());
     }
@@ -2092,9 +2112,41 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(forces_out, c->d_F, 3L * M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    (void)MN;
     ktimer_flush(c);
     c->stats.ms_forces = elapsed_ms(t0);
+    return DDLPB_OK;
+  });
+}
+
+int ddlpb_radius_gradient(ddlpb_ctx* c, double* dedr_out) {
+  if (!c || !dedr_out) return DDLPB_EINVAL;
+  if (c->state < 2) return DDLPB_ESTATE;
+  return guarded([&]() -> int {
+    const int M = c->M, N = c->N;
+    adjoint_fields(c);
+    // buffers of the force terms hold the scalar radius terms: fnb (per neighbour
+    // slot), fself, fpts, fysrc (per sphere); the result goes to F
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_rgrad_switch<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->d_leb,
+                                            c->d_xyz, c->d_rad, c->d_nptr, c->d_nidx, c->d_f, c->d_U, c->d_sgr,
+                                            c->d_yce, c->LUR, c->kappa, c->eta, c->nterms, c->d_X, c->d_xr, c->d_xe,
+                                            c->d_psi, c->d_Phi, c->d_h, c->d_eta, c->d_fnb, c->d_fself));
+    HIPCHK(hipGetLastError());
+    fill(c, c->d_fpts, M, 0.0);
+    if (c->nact > 0) {
+      hipLaunchKernelGGL(k_rgrad_points, dim3(M), dim3(256), 0, c->stream, N, c->d_actptr, c->d_actn, c->d_rad,
+                         c->d_leb, c->d_q, c->eps1, c->eps2, c->d_U, c->d_xr, c->d_eta, c->d_fpt, c->d_fpts);
+      HIPCHK(hipGetLastError());
+    }
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_rgrad_source<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->LY,
+                                            c->d_Y, c->d_leb, c->d_U, c->d_cg, c->d_eta, c->d_lam, c->LP, c->d_m,
+                                            c->d_X, c->d_rtab, c->LUR, c->d_fysrc));
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_rgrad_final, dim3(nblk(M, 256)), dim3(256), 0, c->stream, M, c->d_nptr, c->d_nidx,
+                       c->d_nrev, c->d_fnb, c->d_fself, c->d_fpts, c->d_fysrc, c->d_F);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(dedr_out, c->d_F, (size_t)M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ktimer_flush(c);
     return DDLPB_OK;
   });
 }

@@ -411,3 +411,231 @@ __global__ __launch_bounds__(256) void k_eval_points(int n, const double* __rest
 }
 
 }  // namespace ddlpb
+
+namespace ddlpb {
+
+// ---------------------------------------------------------------- radius gradient
+// dE/dr_k for every sphere from the same frozen functional E_f as the forces (Sec. 3:
+// the adjoint solution differentiates E with respect to any parameter).  The radius
+// r_k enters E_f (i) through the grid points x_k^n = x_k + r_k s_n, which move
+// radially: the derivative is s_n . (gradient with respect to the point), (ii) through
+// t = |x - x_k| / r_k in chi_eta (omega, f, U), and (iii) through the per-degree
+// normalisers of sphere k's bases and constants (Sec. 2.2):
+//   A basis  r_k^-l                        -> -l / r_k
+//   B basis  1 / i_l(kappa r_k)            -> -D_l,  D_l = kappa i_l'/i_l (kappa r_k)
+//   single layer 1 / k_l(kappa r_k)        -> -dk_l, dk_l = kappa k_l'/k_l (kappa r_k)
+//   C_l = (2/pi) kappa r^2 i_l k_l         -> C_l'/C_l = 2/r + D_l + dk_l
+//   y_r = (eps1/eps2) l/r X_r, y_e = -D_l X_e -> -(eps1/eps2) l/r^2 X_r, -D_l' X_e
+// with D_l' = kappa^2 + l(l+1)/r^2 - 2 D_l / r - D_l^2 (modified spherical Bessel
+// equation).  Every per-sphere sum is a fixed-order reduction.
+
+// Switching and A/B basis terms.  Block i (the sphere of the grid points), one
+// neighbour j at a time: rnb[nptr[i] + a] = dE_f/dr_j of the terms evaluated on sphere
+// i's points; rself[i] = the radial motion of those points.  Same quantities as
+// k_force_switch (dT = dE_f/dt_j at the point, V = xi_r vA_j + xi_e vB_j).
+template <int LM>
+__global__ __launch_bounds__(256) void k_rgrad_switch(int M, int N, const double* __restrict__ leb,
+                                                       const double* __restrict__ xyz,
+                                                       const double* __restrict__ rad,
+                                                       const int* __restrict__ nptr, const int* __restrict__ nidx,
+                                                       const double* __restrict__ f, const double* __restrict__ U,
+                                                       const double* __restrict__ sgr, const double* __restrict__ yce,
+                                                       int LUR, double kappa, double eta, int nterms,
+                                                       const double* __restrict__ X, const double* __restrict__ xr,
+                                                       const double* __restrict__ xe, const double* __restrict__ psi,
+                                                       const double* __restrict__ Phi, const double* __restrict__ hg,
+                                                       const double* __restrict__ etag, double* __restrict__ rnb,
+                                                       double* __restrict__ rself) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double s1[kMaxN];
+  __shared__ double sh[16];
+  const int i = blockIdx.x;
+  const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2], ri = rad[i];
+  const int q0 = nptr[i], K = nptr[i + 1] - q0;
+  // S1(x_i^n) = sum_j chi_j V_j where f > 1 (the derivative of d(f) = 1/f)
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    const long in = (long)i * N + n;
+    double acc = 0.0;
+    if (f[in] > 1.0) {
+      const double px = xi + ri * leb[4 * n], py = yi + ri * leb[4 * n + 1], pz = zi + ri * leb[4 * n + 2];
+      for (int a = 0; a < K; ++a) {
+        const int j = nidx[q0 + a];
+        const double irj = 1.0 / rad[j];
+        const double vx = (px - xyz[3 * j]) * irj, vy = (py - xyz[3 * j + 1]) * irj, vz = (pz - xyz[3 * j + 2]) * irj;
+        const double t2 = vx * vx + vy * vy + vz * vz;
+        if (t2 >= 1.0) continue;
+        const double ch = chi_eta(sqrt(t2), eta);
+        if (ch == 0.0) continue;
+        double sg[LM + 1];
+        sigma_weights<LM, double>(kappa * kappa * rad[j] * rad[j] * t2, nterms, sg);
+        const double* Xr = X + (long)j * L;
+        const double* Xe = X + (long)(M + j) * L;
+        double sa = 0.0, pb[LM + 1];
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) pb[l] = 0.0;
+        for_each_solid_harmonic<LM, double>(vx, vy, vz, [&](int l, int idx, double S) { sa += Xr[idx] * S; pb[l] += Xe[idx] * S; });
+        double sb = 0.0;
+#pragma unroll
+        for (int l = 0; l <= LM; ++l) sb += pb[l] * sg[l] / sgr[j * LUR + l];
+        acc += ch * (xr[in] * sa + xe[in] * sb);
+      }
+    }
+    s1[n] = acc;
+  }
+  __syncthreads();
+  double own = 0.0;
+  for (int a = 0; a < K; ++a) {
+    const int j = nidx[q0 + a];
+    const double rj = rad[j], irj = 1.0 / rj;
+    double gj = 0.0;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      const long in = (long)i * N + n;
+      const double sx = leb[4 * n], sy = leb[4 * n + 1], sz = leb[4 * n + 2];
+      const double px = xi + ri * sx, py = yi + ri * sy, pz = zi + ri * sz;
+      const double dx = (px - xyz[3 * j]) * irj, dy = (py - xyz[3 * j + 1]) * irj, dz = (pz - xyz[3 * j + 2]) * irj;
+      const double t2 = dx * dx + dy * dy + dz * dz;
+      if (t2 >= 1.0) continue;
+      const double t = sqrt(t2);
+      const double ch = chi_eta(t, eta), chp = chi_eta_d(t, eta);
+      if (ch == 0.0) continue;
+      const double wn = leb[4 * n + 3];
+      const double fv = f[in], Uv = U[in];
+      const double dv = fv > 1.0 ? 1.0 / fv : 1.0;
+      const double dd = fv > 1.0 ? -1.0 / (fv * fv) : 0.0;
+      using D = Dual<double>;
+      D v[3];
+      v[0] = D(px); v[0].g[0] = 1.0; v[0] = (v[0] - D(xyz[3 * j])) * irj;
+      v[1] = D(py); v[1].g[1] = 1.0; v[1] = (v[1] - D(xyz[3 * j + 1])) * irj;
+      v[2] = D(pz); v[2].g[2] = 1.0; v[2] = (v[2] - D(xyz[3 * j + 2])) * irj;
+      D z2 = (kappa * kappa * rj * rj) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      D sg[LM + 1];
+      sigma_weights<LM, D>(z2, nterms, sg);
+      const double* Xr = X + (long)j * L;
+      const double* Xe = X + (long)(M + j) * L;
+      D sa(0.0), pb[LM + 1];
+      double sal = 0.0;  // sum_l l (A part of degree l): d vA / d r_j = -sal / r_j
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) pb[l] = D(0.0);
+      for_each_solid_harmonic<LM, D>(v[0], v[1], v[2], [&](int l, int idx, const D& S) {
+        sa = sa + Xr[idx] * S;
+        sal += (double)l * Xr[idx] * S.v;
+        pb[l] = pb[l] + Xe[idx] * S;
+      });
+      D sb(0.0);
+      double dsb = 0.0;  // d vB / d r_j = -sum_l D_l (B part of degree l); yce = -D_l
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) {
+        const D bl = (1.0 / sgr[j * LUR + l]) * (pb[l] * sg[l]);
+        sb = sb + bl;
+        dsb += yce[j * LUR + l] * bl.v;
+      }
+      const double xrv = xr[in], xev = xe[in];
+      const double V = xrv * sa.v + xev * sb.v;
+      double dT = 0.5 * wn * (dd * chp * s1[n] + dv * chp * V);
+      if (Uv > 0.0) {
+        const double W = psi[in] * xrv + Phi[in] * (xrv + xev);
+        dT += 0.5 * wn * (W + hg[in] * etag[in]) * chp;
+      }
+      const double om = 0.5 * wn * dv * ch;
+      // radial motion of the point: s . d/dp
+      const double et = irj / t;
+      own += dT * (dx * sx + dy * sy + dz * sz) * et +
+             om * (xrv * (sa.g[0] * sx + sa.g[1] * sy + sa.g[2] * sz) + xev * (sb.g[0] * sx + sb.g[1] * sy + sb.g[2] * sz));
+      // r_j: dt/dr_j = -t / r_j, and the normalisers of the A and B bases
+      gj += dT * (-t * irj) + om * (xrv * (-sal * irj) + xev * dsb);
+    }
+    const double s = block_sum(gj, sh);
+    if (threadIdx.x == 0) rnb[q0 + a] = s;
+  }
+  const double s = block_sum(own, sh);
+  if (threadIdx.x == 0) rself[i] = s;
+}
+
+// Radial motion of the active points of sphere i against the target-side point
+// gradients fpt (psi_0, d_n psi_0 and the single-layer field of the other spheres and
+// charges), plus sphere i's own charge, which stays at x_i while the points move:
+// d/dr (1/r) = -1/r^2, d/dr (s . grad 1/|x - x_i|) = 2/r^3.
+__global__ __launch_bounds__(256) void k_rgrad_points(int N, const int* __restrict__ act_ptr,
+                                                      const int* __restrict__ act_n, const double* __restrict__ rad,
+                                                      const double* __restrict__ leb, const double* __restrict__ q,
+                                                      double eps1, double eps2, const double* __restrict__ U,
+                                                      const double* __restrict__ xr, const double* __restrict__ etag,
+                                                      const double* __restrict__ fpt, double* __restrict__ out) {
+  __shared__ double sh[32];
+  const int i = blockIdx.x;
+  const double ri = rad[i], qi = q[i];
+  const double o1 = -qi / (ri * ri), o2 = 2.0 * qi / (ri * ri * ri);
+  Comp acc;
+  for (int k = act_ptr[i] + threadIdx.x; k < act_ptr[i + 1]; k += blockDim.x) {
+    const int n = act_n[k];
+    const long in = (long)i * N + n;
+    const double c = -0.5 * leb[4 * n + 3] * U[in];
+    const double a1 = c * xr[in] / eps1, a2 = c * etag[in] / eps2;
+    acc.add(fpt[3L * k] * leb[4 * n] + fpt[3L * k + 1] * leb[4 * n + 1] + fpt[3L * k + 2] * leb[4 * n + 2]);
+    acc.add(a1 * o1 + a2 * o2);
+  }
+  const double s = block_sum_comp(acc, sh);
+  if (threadIdx.x == 0) out[i] = s;
+}
+
+// Normaliser terms of sphere j's single layer (block j):
+//   1/2 sum_lm dk_l m_jlm lambda'_jlm - 1/2 sum_lm (C_l'/C_l) m_jlm lambda_jlm
+//   + 1/2 sum_lm ((eps1/eps2) l/r^2 X_r,jlm + D_l' X_e,jlm) mu_jlm
+// with lambda = lambda' + An_j(c_j) (own sphere added back, c = w U xi_s) and
+// mu = sum_n w_n U_j eta_j Y_lm(s_n).  rtab [4][M][LUR]: dk_l, C_l'/C_l,
+// (eps1/eps2) l/r^2, D_l'.
+template <int LM>
+__global__ __launch_bounds__(256) void k_rgrad_source(int M, int N, int LY, const double* __restrict__ Y,
+                                                      const double* __restrict__ leb, const double* __restrict__ U,
+                                                      const double* __restrict__ cgrid,
+                                                      const double* __restrict__ etag,
+                                                      const double* __restrict__ lamp, int LLAM,
+                                                      const double* __restrict__ m, const double* __restrict__ X,
+                                                      const double* __restrict__ rtab, int LUR,
+                                                      double* __restrict__ out) {
+  constexpr int L = (LM + 1) * (LM + 1);
+  __shared__ double cg[kMaxN], ue[kMaxN];
+  __shared__ double sh[16];
+  const int j = blockIdx.x;
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    const long jn = (long)j * N + n;
+    cg[n] = cgrid[jn];
+    ue[n] = leb[4 * n + 3] * U[jn] * etag[jn];
+  }
+  __syncthreads();
+  const long MU = (long)M * LUR;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    const int l = deg_of(t);
+    double own = 0.0, mu = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double y = Y[(long)n * LY + t];
+      own += cg[n] * y;
+      mu += ue[n] * y;
+    }
+    const long jl = (long)j * LUR + l;
+    const double lp = lamp[(long)j * LLAM + t], mj = m[(long)j * L + t];
+    acc += 0.5 * rtab[jl] * mj * lp - 0.5 * rtab[MU + jl] * mj * (lp + own) +
+           0.5 * (rtab[2 * MU + jl] * X[(long)j * L + t] + rtab[3 * MU + jl] * X[(long)(M + j) * L + t]) * mu;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// dE/dr_k = rself + rpts + rsrc + the switching terms of the spheres that have k as a
+// neighbour, gathered in a fixed order
+__global__ void k_rgrad_final(int M, const int* __restrict__ nptr, const int* __restrict__ nidx,
+                              const int* __restrict__ nrev, const double* __restrict__ rnb,
+                              const double* __restrict__ rself, const double* __restrict__ rpts,
+                              const double* __restrict__ rsrc, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  Comp g;
+  g.add(rself[k]);
+  g.add(rpts[k]);
+  g.add(rsrc[k]);
+  for (int b = nptr[k]; b < nptr[k + 1]; ++b) g.add(rnb[nptr[nidx[b]] + nrev[b]]);
+  out[k] = g.value();
+}
+
+}  // namespace ddlpb

@@ -39,3 +39,71 @@ def test_dielectric_gradient_scaling_identity_fmm():
     ctx.adjoint(1e-10)
     g = ctx.dielectric_gradient()
     assert abs(1.0 * g[0] + 78.54 * g[1] + E) < 1e-8 * abs(E)
+
+
+# ------------------------------------------------------------ radius gradient
+def test_radius_gradient_single_sphere():
+    """dE/da = -E/a - q^2 kappa / (2 a eps_out (1 + kappa a)^2) for one sphere with a
+    centred charge."""
+    a, q, kap, e1, e2 = 1.7, 0.8, 0.3, 2.0, 60.0
+    ctx = Context([[0.3, 0.1, -0.2]], [a], [q], eps_in=e1, eps_out=e2, kappa=kap, lmax=6, n_lebedev=110)
+    ctx.solve(1e-12)
+    ctx.adjoint(1e-12)
+    E = q * q / (2 * a) * (1 / (e2 * (1 + kap * a)) - 1 / e1)
+    ref = -E / a - q * q * kap / (2 * a * e2 * (1 + kap * a) ** 2)
+    assert abs(ctx.radius_gradient()[0] / ref - 1) < 1e-10
+
+
+@pytest.mark.parametrize("seed,lmax,nleb,e1", [(0, 6, 110, 1.0), (3, 6, 110, 2.0), (2, 8, 302, 1.0)])
+def test_radius_gradient_vs_oracle(seed, lmax, nleb, e1):
+    """Every dE/dr_j of the adjoint assembly equals the oracle's complex step of the
+    dense solve (direct sums on the GPU)."""
+    x, r, q = inputs.small_cluster(seed)
+    ctx = Context(x, r, q, eps_in=e1, lmax=lmax, n_lebedev=nleb)
+    ctx.solve(1e-12)
+    ctx.adjoint(1e-12)
+    g = ctx.radius_gradient()
+    P = oracle.Problem(x, r, q, e1, 78.54, 0.104, lmax=lmax, n_lebedev=nleb)
+    atoms = list(range(len(r))) if lmax < 8 else [0, 4, 7, 11]
+    ref = P.radius_gradient(atoms)
+    assert np.abs(g[atoms] - ref).max() < 1e-8 * np.abs(ref).max(), np.abs(g[atoms] - ref).max() / np.abs(ref).max()
+
+
+def test_radius_gradient_fmm_matches_direct():
+    """With the FMM (p = 12) the radius gradient stays within the far-field accuracy of
+    the direct sums."""
+    x, r, q = inputs.lattice_cluster(700, seed=5)
+    out = []
+    for p in (0, 12):
+        ctx = Context(x, r, q, lmax=6, n_lebedev=302, fmm_order=p)
+        ctx.solve(1e-11)
+        ctx.adjoint(1e-11)
+        out.append(ctx.radius_gradient())
+        ctx.close()
+    assert np.abs(out[1] - out[0]).max() < 1e-6 * np.abs(out[0]).max()
+
+
+def test_radius_gradient_scaling_identity_fmm():
+    """E(s x, s r, kappa / s) = E / s, so -sum x . F + sum r dE/dr - kappa dE/dkappa = -E,
+    with the analytical forces and radius derivatives and dE/dkappa from central
+    differences of two more solves (2,000 atoms, lmax 8, 302 points, FMM p = 12)."""
+    x, r, q = inputs.lattice_cluster(2000, seed=2)
+    kap = 0.104
+
+    def ctx_for(k):
+        return Context(x, r, q, kappa=k, lmax=8, n_lebedev=302, fmm_order=12)
+
+    ctx = ctx_for(kap)
+    E = ctx.solve(1e-10)
+    ctx.adjoint(1e-10)
+    F, gr = ctx.forces(), ctx.radius_gradient()
+    ctx.close()
+    h = 1e-4 * kap
+    Ek = []
+    for k in (kap + h, kap - h):
+        c2 = ctx_for(k)
+        Ek.append(c2.solve(1e-11))
+        c2.close()
+    dk = (Ek[0] - Ek[1]) / (2 * h)
+    lhs = -(x * F).sum() + (r * gr).sum() - kap * dk
+    assert abs(lhs / -E - 1) < 1e-5, (lhs, -E)
