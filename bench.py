@@ -286,6 +286,15 @@ def main():
                 "launches_per_step": nl / args.steps, "ms_per_launch": ms / nl if nl else 0.0,
                 "flops_per_launch": work / nl if nl else 0.0}
 
+    def roof_mfma(name):
+        # the dense table products on the FP64 matrix cores: algorithmic 2 N L flops per
+        # row and table (unpadded), against the FP64 matrix peak
+        ms, nl, work = kt[name]
+        achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        return {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "launches_per_step": nl / args.steps,
+                "ms_per_launch": ms / nl if nl else 0.0, "flops_per_launch": work / nl if nl else 0.0}
+
     name, (ms, nl, work) = tops[0]
     out = {
         "metric": "energy+forces atoms/sec at 100k atoms, tol 1e-6; served p50/p99 latency",
@@ -303,6 +312,7 @@ def main():
                    "precision": args.precision, "tol": args.tol, "options": extra},
         "roofline": roof(name, ms, nl, work),
         "roofline_top3": [roof(k, *v) for k, v in tops],
+        "roofline_mfma": [roof_mfma(k) for k in ("syn_gemm", "an_gemm") if k in kt],
         "energy": E, "iters": [st["iters_primal"], st["iters_adjoint"]], "cap_pairs": st["n_cap_pairs"],
         "residuals": [st["resid_primal"], st["resid_adjoint"]],
         "phase_ms": {k: st[k] for k in ("ms_rhs", "ms_primal", "ms_adjoint", "ms_forces")},
@@ -322,6 +332,7 @@ def main():
                         "energy_rel_err_vs_fp64": abs(Em - E) / abs(E),
                         "force_rel_err_vs_fp64": float(np.abs(Fm - F).max() / np.abs(F).max()),
                         "iters": [mst["iters_primal"], mst["iters_adjoint"]],
+                        "fp64_iters_after_fp32_adjoint": mst["refinements"],
                         "residuals": [mst["resid_primal"], mst["resid_adjoint"]],
                         "kernels_ms_per_step": {k: v[0] / args.mixed_steps
                                                 for k, v in sorted(mkt.items(), key=lambda kv: -kv[1][0])[:12]}}

@@ -62,7 +62,7 @@ typedef struct {
   int64_t n_m2l;             /* multipole-to-local translations per field evaluation */
   int32_t fmm_order;         /* 0 = direct summation */
   int32_t precision;         /* 0 = FP64, 1 = mixed */
-  int32_t refinements;       /* FP64 refinement steps of the mixed path */
+  int32_t refinements;       /* mixed paths: FP64 iterations (precision 1) or refinement steps (2) */
   int32_t fmm_order_below_lmax; /* 1 if 0 < fmm_order < lmax (forces inaccurate, Sec. 4.1.2) */
 } ddlpb_stats;
 
@@ -199,14 +199,21 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    1 = mixed: the preconditioner (the Krylov steps on L_AB and
  *                    their Jacobi sweeps) runs the near-field A/B kernels in FP32;
  *                    flexible GMRES on the FP64 operator (FP64 residual, vectors,
- *                    orthogonalisation, norms) restores the tolerance.
+ *                    orthogonalisation, norms) restores the tolerance.  With
+ *                    option mixed_near_sl = 1 (and the FMM), the outer iterations
+ *                    also apply the near single layer (the directly summed sphere
+ *                    pairs of the C part) in FP32 (FP32 per pair, FP64 sums), and
+ *                    then the FP64 operator's residual b - L x decides: flexible
+ *                    GMRES continues on the FP64 operator from x until it meets
+ *                    tol (stats.refinements counts those FP64 iterations of the
+ *                    last solve).
  *                    2 = mixed with FP32 operator: FP64 iterative refinement (FP64
  *                    residual b - L x) around GMRES solves of the correction
  *                    equation in which the near-field kernels (operator and
  *                    sweeps) compute in FP32 (stats.refinements counts the steps).
- *                    In both, Bessel ratios, the FMM, the single-layer sums, the
- *                    energy and the forces stay FP64.  Both need the cap lists
- *                    (else FP64 is used).
+ *                    In both, Bessel ratios, the FMM translations, the energy and
+ *                    the forces stay FP64.  Both need the cap lists (else FP64 is
+ *                    used).
  *   "gmres_restart"  outer Krylov subspace size (1..200)
  *   "inner_sweeps"   Jacobi sweeps on L_AB = [A 0; 0 B] used as the innermost
  *                    preconditioner (0..64; Sec. 4 uses L_AB as preconditioner)
@@ -236,8 +243,12 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    (gmres_restart - 3) / 4, the histories use the GMRES basis)
  *   "warm_start"     1 (default): solves start from the previous X / X_adj;
  *                    0: every solve starts from zero
- *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field kernels of the mixed
- *                    path (diagnostic: operator error of the mixed path)
+ *   "mixed_near_sl"  1: precision 1 with the FMM applies the near single layer
+ *                    of the outer iterations in FP32 (see "precision"); 0 (default)
+ *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field A/B kernels of the
+ *                    mixed preconditioner; 2: the FP32 near single layer of the
+ *                    mixed outer iterations (FMM only); 0: FP64 (diagnostic:
+ *                    operator error of the mixed path)
  *   "m2l_waves"      wavefronts per block of the wavefront multipole-to-local
  *                    kernel (0 = chosen from the occupancy calculator; 1, 2, 4,
  *                    8, 16; -1 = the one-node-per-block kernel built on the

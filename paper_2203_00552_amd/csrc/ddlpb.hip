@@ -3,7 +3,6 @@
 // Call order (Sec. 3.1, final summary of the force computation): ddlpb_setup ->
 // ddlpb_solve (primal L X = g) -> ddlpb_adjoint (L^T X_adj = Q) -> ddlpb_forces.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -24,6 +23,7 @@
 #include "kernels_forces.hpp"
 #include "fmm.hpp"
 #include "fmm_host.hpp"
+#include "gemm_mfma.hpp"
 #include "fmm_lane_api.hpp"
 #include "near_lane_api.hpp"
 
@@ -41,12 +41,6 @@ struct HipError {
     hipError_t err__ = (x);                        \
     if (err__ != hipSuccess) throw HipError{err__}; \
   } while (0)
-#define BLASCHK(x)                                                            \
-  do {                                                                        \
-    rocblas_status st__ = (x);                                                \
-    if (st__ != rocblas_status_success) throw HipError{hipErrorUnknown};      \
-  } while (0)
-
 // One-time upload of the Legendre recurrence constants per device.
 std::mutex g_const_mu;
 std::map<int, bool> g_const_done;
@@ -60,6 +54,12 @@ void ensure_constants() {
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_pmm), pmm.data(), pmm.size() * sizeof(double)));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_ra), ra.data(), ra.size() * sizeof(double)));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_rb), rb.data(), rb.size() * sizeof(double)));
+  {
+    std::vector<float> pf(pmm.begin(), pmm.end()), af(ra.begin(), ra.end()), bf(rb.begin(), rb.end());
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_pmm_f), pf.data(), pf.size() * sizeof(float)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_ra_f), af.data(), af.size() * sizeof(float)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_rb_f), bf.data(), bf.size() * sizeof(float)));
+  }
   std::vector<double> sinv((kLmaxDev + 2) * kSigTerms);
   for (int l = 0; l <= kLmaxDev + 1; ++l)
     for (int k = 0; k < kSigTerms; ++k) sinv[l * kSigTerms + k] = 0.5 / ((k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
@@ -113,12 +113,14 @@ struct ddlpb_ctx {
   // ---- options
   int precision = 0, restart = 100, sweeps = 1, maxit = 400;
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
+  bool sl32 = false;          // near single layer of the operator in FP32 (outer iterations of precision 1)
+  int fp64_iters = 0;         // FP64 outer iterations after the FP32 ones in the last solve (precision 1)
+  bool mixed_sl = false;      // precision 1: outer iterations with the FP32 near single layer (option mixed_near_sl)
   double *d_rr = nullptr, *d_dd = nullptr;
   double* d_YT = nullptr;
   double* d_WY = nullptr;     // w_n Y_lm(s_n), [N][L] (column-major L x N): the An projection as a GEMM
   double* d_Vpt = nullptr;    // point values of the A/B sums, [2M][N], input of the An GEMM
-  rocblas_handle blas = nullptr;
-  bool apply_fp32 = false;    // ddlpb_apply with the FP32 near-field kernels (diagnostic)
+  int apply_fp32 = 0;         // ddlpb_apply: 1 FP32 near-field A/B kernels, 2 FP32 near single layer (diagnostic)
   int pkrylov = 6;            // > 0: preconditioner = this many GMRES steps on L_AB (flexible outer)
   int solver = 0;             // 0: GMRES, 1: Jacobi-DIIS (the paper's macro/micro iterations)
   int diis_max = 8;           // DIIS history length
@@ -159,7 +161,7 @@ struct ddlpb_ctx {
   int *d_nptr = nullptr, *d_nidx = nullptr, *d_nrev = nullptr;
   double *d_f = nullptr, *d_U = nullptr;
   int *d_actcnt = nullptr, *d_actptr = nullptr, *d_actsph = nullptr, *d_actn = nullptr;
-  double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_kr = nullptr;
+  double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_iur = nullptr, *d_kr = nullptr;
   double *d_dtab = nullptr;
   double *d_rtab = nullptr;  // radius derivatives of the radial constants [4][M][LUR]
   double *d_m = nullptr, *d_lam = nullptr;
@@ -384,6 +386,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_sgr = cv.take<double>(M * c->LUR);
   c->d_isgr = cv.take<double>(M * c->LUR);
   c->d_ur = cv.take<double>(M * c->LUR);
+  c->d_iur = cv.take<double>(M * c->LUR);  // 1 / ur
   c->d_kr = cv.take<double>(M * c->LUR);
   c->d_dtab = cv.take<double>(3 * (size_t)c->L * c->LP);
   c->d_rtab = cv.take<double>(4 * (size_t)M * c->LUR);
@@ -585,10 +588,28 @@ inline double flops_sl_pair(int lm) { double L = (lm + 1.0) * (lm + 1.0); return
 // the i_l weights (two series of nterms terms and the downward recurrence)
 inline double flops_cap_pair(int lm, int nterms) { double L = (lm + 1.0) * (lm + 1.0); return 7.0 * L + 6.0 * nterms + 8.0 * (lm + 1) + 30.0; }
 
-rocblas_handle blas(ddlpb_ctx* c) {
-  if (!c->blas) BLASCHK(rocblas_create_handle(&c->blas));
-  BLASCHK(rocblas_set_stream(c->blas, c->stream));
-  return c->blas;
+// out (R x C, ldo) = A (R x K, lda) B (K x C, ldb) + c0 base (base null: no term), FP64
+// matrix cores (k_gemm_f64): 16 S rows of A per block in LDS, S = 4, 2 or 1, the largest
+// whose chunk fits 80 KB (two blocks per compute unit)
+void gemm_f64(ddlpb_ctx* c, int R, int C, int K, const double* A, int lda, const double* B, int ldb,
+              const double* base, double c0, double* out, int ldo) {
+  if (R <= 0 || C <= 0) return;
+  int S = 4;
+  while (S > 1 && gemm_f64_lds(S, K) > 80 * 1024) S /= 2;
+  const size_t lds = gemm_f64_lds(S, K);
+  if (lds > 160 * 1024) throw HipError{hipErrorInvalidValue};
+  const int nw = std::min(kGemmWaves, (C + 15) / 16);
+  const dim3 grid((unsigned)((R + 16 * S - 1) / (16 * S))), block(64 * nw);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(kern, grid, block, lds, c->stream, R, C, K, A, lda, B, ldb, base, c0, out, ldo);
+  };
+  if (S == 4) go(k_gemm_f64<4>);
+  else if (S == 2) go(k_gemm_f64<2>);
+  else go(k_gemm_f64<1>);
+  HIPCHK(hipGetLastError());
 }
 void fill(ddlpb_ctx* c, double* p, long n, double v) {
   if (n <= 0) return;
@@ -651,20 +672,9 @@ void launch_LX_caps(ddlpb_ctx* c, const double* base, double c0, const double* n
   HIPCHK(hipGetLastError());
   if (gemm) an_gemm(c, base, c0, out);
 }
-// out = c0 base + An(point values in d_Vpt): (L x 2M) = WY (L x N) x Vpt (N x 2M), column-major
+// out = c0 base + An(point values in d_Vpt): [2M][L] = Vpt [2M][N] x WY [N][L]
 void an_gemm(ddlpb_ctx* c, const double* base, double c0, double* out) {
-  const long D = 2L * c->M * c->L;
-  double beta = 0.0;
-  if (base == out) {
-    beta = c0;
-  } else if (base) {
-    hipLaunchKernelGGL(k_scale, dim3(nblk(D, 256)), dim3(256), 0, c->stream, D, c0, base, out);
-    HIPCHK(hipGetLastError());
-    beta = 1.0;
-  }
-  const double one = 1.0;
-  BLASCHK(rocblas_dgemm(blas(c), rocblas_operation_none, rocblas_operation_none, c->L, 2 * c->M, c->N, &one, c->d_WY,
-                        c->L, c->d_Vpt, c->N, &beta, out, c->L));
+  gemm_f64(c, 2 * c->M, c->L, c->N, c->d_Vpt, c->N, c->d_WY, c->L, base, c0, out, c->L);
 }
 template <class R>
 void launch_LTZ_caps(ddlpb_ctx* c, const double* base, double c0, const double* zr, const double* ze, double c1,
@@ -716,12 +726,9 @@ void apply_LX(ddlpb_ctx* c, const double* base, double c0, const double* nearX, 
 
 void syn2(ddlpb_ctx* c, const double* Z, int mode, double* o1, double* o2) {
   if (mode == 0 && o1 == c->d_zr && o2 == c->d_ze) {
-    // Syn of every sphere at once: [2M][N] = Z [2M][L] x Y^T, one DGEMM (column-major:
-    // (N x 2M) = Y(L x N, lda LY)^T (L x 2M))
+    // Syn of every sphere at once: [2M][N] = Z [2M][L] x Y^T, with Y^T = YT [LY][N]
     KScope ks(c, "syn_gemm", 2.0 * c->N * c->L * 2.0 * c->M);
-    const double one = 1.0, zero = 0.0;
-    BLASCHK(rocblas_dgemm(blas(c), rocblas_operation_transpose, rocblas_operation_none, c->N, 2 * c->M, c->L, &one,
-                          c->d_Y, c->LY, Z, c->L, &zero, c->d_zr, c->N));
+    gemm_f64(c, 2 * c->M, c->N, c->L, Z, c->L, c->d_YT, c->N, nullptr, 0.0, c->d_zr, c->N);
     return;
   }
   const int nt = std::min(512, (c->N + 63) / 64 * 64);
@@ -776,12 +783,12 @@ void sl_field_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double*
   if (grad) {
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
                                             c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
-                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_ur, c->LUR, c->kappa,
+                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_iur, c->LUR, c->kappa,
                                             exclude_self, accumulate, out));
   } else {
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, false>), dim3(nblk(c->nact, 256)), dim3(256), 0,
                                             c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
-                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_ur, c->LUR, c->kappa,
+                                            c->d_rad, c->d_leb, lptr, lidx, m, c->d_iur, c->LUR, c->kappa,
                                             exclude_self, accumulate, out));
   }
   HIPCHK(hipGetLastError());
@@ -790,7 +797,7 @@ void sl_adjoint_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const doubl
                      int accumulate, int ldl, double* lam) {
   KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pairs_pts);
   LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
-                                     c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_ur,
+                                     c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_iur,
                                      c->LUR, c->kappa, exclude_self, accumulate, ldl, lam));
   HIPCHK(hipGetLastError());
 }
@@ -1115,11 +1122,17 @@ void sl_field_full(ddlpb_ctx* c, const double* m, double* Phi) {
   if (c->fmm_order == 0) { sl_field(c, m, false, 0, Phi); return; }
   fill(c, Phi, (long)c->M * c->N, 0.0);
   if (c->nact == 0) return;
-  {
+  if (c->sl32) {
+    KScope ks(c, "sl_near_f32", flops_sl_pair(c->lmax) * c->near_pts_fmm);
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, false, float>), dim3(nblk(c->nact, 256)),
+                                            dim3(256), 0, c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn,
+                                            c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, m, c->d_iur, c->LUR,
+                                            c->kappa, 0, 1, Phi));
+  } else {
     KScope ks(c, "sl_near", flops_sl_pair(c->lmax) * c->near_pts_fmm);
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, false>), dim3(nblk(c->nact, 256)), dim3(256), 0,
                                             c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
-                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, m, c->d_ur, c->LUR, c->kappa, 0, 1,
+                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, m, c->d_iur, c->LUR, c->kappa, 0, 1,
                                             Phi));
   }
   fmm_forward(c, 0, m, c->lmax, c->L, c->d_SL);
@@ -1128,11 +1141,17 @@ void sl_field_full(ddlpb_ctx* c, const double* m, double* Phi) {
 // lambda (degree lo, stride ldl) from grid charges: direct, or FMM near list + far field
 void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, int ldl, double* lam) {
   if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
-  {
+  if (c->sl32 && lo == c->lmax) {
+    KScope ks(c, "sl_near_adjoint_f32", flops_sl_pair(lo) * c->near_pts_fmm);
+    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc, float>), dim3(c->M), dim3(256), 0, c->stream, c->M,
+                                       c->N, c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni,
+                                       cgrid, c->d_iur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
+    HIPCHK(hipGetLastError());
+  } else {
     KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pts_fmm);
     LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
                                        c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, cgrid,
-                                       c->d_ur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
+                                       c->d_iur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
     HIPCHK(hipGetLastError());
   }
   p2l_dual(c, cgrid, nullptr, c->d_Lam);
@@ -1336,8 +1355,32 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
       c->cur_prec = keep;
       c->inner_total += it;
     };
-    return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
-                      c->d_t1, c->d_t2, iters, relres);
+    if (!fp32 || c->fmm_order == 0 || !c->mixed_sl)
+      return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
+                        c->d_t1, c->d_t2, iters, relres);
+    // mixed path with the FMM: the outer iterations apply the operator with its near
+    // single layer in FP32; then the FP64 operator's residual b - L x decides, and
+    // flexible GMRES continues from x on the FP64 operator until it meets tol (the
+    // FP64 outer refinement; usually the check alone)
+    struct Sl32 {
+      ddlpb_ctx* c;
+      explicit Sl32(ddlpb_ctx* cc) : c(cc) { c->sl32 = true; }
+      ~Sl32() { c->sl32 = false; }
+    };
+    VecOp opLm = [&](const double* in, double* out) {
+      Sl32 g(c);
+      opL(in, out);
+    };
+    int it1 = 0;
+    double rr1 = 0.0;
+    (void)gmres_core(c, opLm, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
+                     c->d_t1, c->d_t2, &it1, &rr1);
+    int it2 = 0;
+    const int rc = gmres_core(c, opL, inner, b, x, tol, c->restart, std::max(0, c->maxit - it1), 1 << 30, false,
+                              c->d_V, c->d_Z, c->d_w, c->d_t1, c->d_t2, &it2, relres);
+    *iters = it1 + it2;
+    c->fp64_iters += it2;
+    return rc;
   }
   if (c->precision == 1 && c->use_caps && c->pdelta < 0.0) {
     // FP32 Jacobi sweeps as the preconditioner of flexible GMRES on the FP64 operator:
@@ -1386,8 +1429,10 @@ int solve_system(ddlpb_ctx* c, bool transpose, const double* b, double* x, doubl
     return diis_solve(c, transpose, b, x, tol, iters, relres);
   }
   if (c->precision != 2 || !c->use_caps || !c->d_rr) {
-    c->stats.refinements = 0;
-    return gmres(c, transpose, b, x, tol, iters, relres);
+    c->fp64_iters = 0;
+    const int rc = gmres(c, transpose, b, x, tol, iters, relres);
+    c->stats.refinements = c->fp64_iters;
+    return rc;
   }
   const long D = 2L * c->M * c->L;
   const double bn = norm2(c, b);
@@ -1660,6 +1705,9 @@ void upload_and_init(ddlpb_ctx* c) {
   for (size_t k = 0; k < sgr.size(); ++k) isgr[k] = sgr[k] != 0.0 ? 1.0 / sgr[k] : 0.0;
   up(c->d_isgr, isgr.data(), isgr.size() * sizeof(double));
   up(c->d_ur, ur.data(), ur.size() * sizeof(double));
+  std::vector<double> iur(ur.size());
+  for (size_t k = 0; k < ur.size(); ++k) iur[k] = ur[k] != 0.0 ? 1.0 / ur[k] : 0.0;
+  up(c->d_iur, iur.data(), iur.size() * sizeof(double));
   up(c->d_kr, kr.data(), kr.size() * sizeof(double));
   up(c->d_dtab, dtab.data(), dtab.size() * sizeof(double));
   if (c->fmm_order > 0) {
@@ -1927,7 +1975,7 @@ void adjoint_fields(ddlpb_ctx* c) {
     KScope ks(c, "sl_near_grad", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
                                             c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn, c->d_xyz,
-                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_ur, c->LUR,
+                                            c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_iur, c->LUR,
                                             c->kappa, 1, 0, c->d_gphi));
     HIPCHK(hipGetLastError());
   }
@@ -2320,7 +2368,6 @@ int ddlpb_dielectric_gradient(ddlpb_ctx* c, double* dedeps_out) {
 
 void ddlpb_free(ddlpb_ctx* c) {
   if (!c) return;
-  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->ws_owned && c->ws) (void)hipFree(c->ws);
   if (c->d_cache) (void)hipFree(c->d_cache);
   for (auto& p : c->ev_pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
@@ -2368,8 +2415,12 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 0 && v <= 64)) return DDLPB_EINVAL;
     c->pkrylov = (int)v;
+  } else if (k == "mixed_near_sl") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->mixed_sl = v != 0;
   } else if (k == "apply_fp32") {
-    c->apply_fp32 = v != 0;
+    if (!(v == 0 || v == 1 || v == 2)) return DDLPB_EINVAL;
+    c->apply_fp32 = (int)v;
   } else if (k == "m2l_waves") {
     if (!(v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
     c->m2l_waves = (int)v;
@@ -2614,9 +2665,17 @@ int ddlpb_apply(ddlpb_ctx* c, int32_t transpose, const double* x_in, double* y_o
     if (rc) return rc;
     const size_t D = 2L * c->M * c->L;
     HIPCHK(hipMemcpyAsync(c->d_t2, x_in, D * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    c->cur_prec = c->apply_fp32 ? 1 : 0;
-    if (transpose) op_LT(c, c->d_t2, c->d_w); else op_L(c, c->d_t2, c->d_w);
+    c->cur_prec = c->apply_fp32 == 1 ? 1 : 0;
+    c->sl32 = c->apply_fp32 == 2;
+    try {
+      if (transpose) op_LT(c, c->d_t2, c->d_w); else op_L(c, c->d_t2, c->d_w);
+    } catch (...) {
+      c->cur_prec = 0;
+      c->sl32 = false;
+      throw;
+    }
     c->cur_prec = 0;
+    c->sl32 = false;
     HIPCHK(hipMemcpyAsync(y_out, c->d_w, D * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DDLPB_OK;

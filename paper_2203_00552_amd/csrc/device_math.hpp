@@ -28,6 +28,10 @@ __host__ __device__ constexpr int lmi(int l, int m) { return l * l + l + m; }
 __constant__ double c_pmm[kLmaxDev + 1];
 __constant__ double c_ra[kTri];
 __constant__ double c_rb[kTri];
+// the same constants rounded to FP32, for the single-precision kernels of the mixed path
+__constant__ float c_pmm_f[kLmaxDev + 1];
+__constant__ float c_ra_f[kTri];
+__constant__ float c_rb_f[kTri];
 // Coefficients of the sigma_l series: c_sinv[l * kSigTerms + k] = 1 / (2 (k+1) (2l+2k+3)).
 constexpr int kSigTerms = 64;
 __constant__ double c_sinv[(kLmaxDev + 2) * kSigTerms];
@@ -85,10 +89,14 @@ __device__ __forceinline__ void for_each_solid_harmonic(const T& x, const T& y, 
     T p2(R(0)), p1(R(0));
 #pragma unroll
     for (int l = m; l <= LM; ++l) {
+      constexpr bool f32 = sizeof(R) == 4;
+      const R pmm = f32 ? R(c_pmm_f[m]) : R(c_pmm[m]);
+      const R ra = f32 ? R(c_ra_f[tri(l, m)]) : R(c_ra[tri(l, m)]);
+      const R rb = f32 ? R(c_rb_f[tri(l, m)]) : R(c_rb[tri(l, m)]);
       T p;
-      if (l == m) p = T(R(c_pmm[m]));
-      else if (l == m + 1) p = R(c_ra[tri(l, m)]) * (z * p1);
-      else p = R(c_ra[tri(l, m)]) * (z * p1) - R(c_rb[tri(l, m)]) * (r2 * p2);
+      if (l == m) p = T(pmm);
+      else if (l == m + 1) p = ra * (z * p1);
+      else p = ra * (z * p1) - rb * (r2 * p2);
       if (m == 0) {
         f(l, lmi(l, 0), p);
       } else {

@@ -254,42 +254,69 @@ __global__ __launch_bounds__(256) void k_sl_adjoint_direct(int M, int N, int nac
 // ------------------------------------------- single-layer field (listed pairs)
 // Same field as k_sl_field_direct, restricted to the source spheres listed for the
 // target point's own sphere (CSR lptr/lidx): the near part of a split evaluation.
-template <int LM, bool GRAD>
+// R is the compute type of one (point, sphere) interaction: double, or float on the
+// mixed path, where the offset x - x_j is formed in FP64 and rounded once, the weights
+// and harmonics of the pair run in FP32 and the sum over the listed spheres is FP64.
+// iur = 1 / u_l(r_j) [M][LUR].
+template <class R>
+__device__ __forceinline__ R recip(double x) {
+  if constexpr (sizeof(R) == 8) return 1.0 / x;
+  else return __builtin_amdgcn_rcpf((float)x);
+}
+__device__ __forceinline__ double widen(float x) { return (double)x; }
+__device__ __forceinline__ Dual<double> widen(const Dual<float>& x) {
+  Dual<double> r;
+  r.v = x.v;
+  for (int a = 0; a < 3; ++a) r.g[a] = x.g[a];
+  return r;
+}
+template <int LM, bool GRAD, class R = double>
 __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, const int* __restrict__ act_sph,
                                                         const int* __restrict__ act_n, const double* __restrict__ xyz,
                                                         const double* __restrict__ rad, const double* __restrict__ leb,
                                                         const int* __restrict__ lptr, const int* __restrict__ lidx,
-                                                        const double* __restrict__ m, const double* __restrict__ ur,
+                                                        const double* __restrict__ m, const double* __restrict__ iur,
                                                         int LUR, double kappa, int exclude_self, int accumulate,
                                                         double* __restrict__ out) {
   constexpr int L = (LM + 1) * (LM + 1);
+  constexpr bool f64 = sizeof(R) == 8;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nact) return;
   const int i = act_sph[k], n = act_n[k];
   double p[3];
   for (int a = 0; a < 3; ++a) p[a] = xyz[3 * i + a] + rad[i] * leb[4 * n + a];
-  using T = typename std::conditional<GRAD, Dual<double>, double>::type;
-  T acc(0.0);
+  using T = typename std::conditional<GRAD, Dual<R>, R>::type;
+  using A = typename std::conditional<GRAD, Dual<double>, double>::type;
+  A acc(0.0);
   for (int q = lptr[i]; q < lptr[i + 1]; ++q) {
     const int j = lidx[q];
     if (exclude_self && j == i) continue;
-    const double rj = rad[j], irj = 1.0 / rj;
+    const double rj = rad[j];
+    const R irj = recip<R>(rj);
     T v[3];
     for (int a = 0; a < 3; ++a) {
-      v[a] = T(p[a]);
-      if constexpr (GRAD) v[a].g[a] = 1.0;
-      v[a] = (v[a] - T(xyz[3 * j + a])) * irj;
+      v[a] = T(R(p[a] - xyz[3 * j + a]));
+      if constexpr (GRAD) v[a].g[a] = R(1);
+      v[a] = v[a] * irj;
     }
-    T rho = dsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * rj;
+    T rho = dsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) * R(rj);
     T u[LM + 1];
     k_weights<LM, T>(rho, kappa, u);
     const double* mc = m + (long)j * L;
     T part[LM + 1];
 #pragma unroll
-    for (int l = 0; l <= LM; ++l) part[l] = T(0.0);
-    for_each_solid_harmonic<LM, T>(v[0], v[1], v[2], [&](int l, int idx, const T& S) { part[l] = part[l] + mc[idx] * S; });
+    for (int l = 0; l <= LM; ++l) part[l] = T(R(0));
+    for_each_solid_harmonic<LM, T>(v[0], v[1], v[2],
+                                   [&](int l, int idx, const T& S) { part[l] = part[l] + R(mc[idx]) * S; });
+    if constexpr (f64) {
 #pragma unroll
-    for (int l = 0; l <= LM; ++l) acc = acc + (u[l] * (1.0 / ur[j * LUR + l])) * part[l];
+      for (int l = 0; l <= LM; ++l) acc = acc + (u[l] * iur[j * LUR + l]) * part[l];
+    } else {
+      T sj(R(0));
+#pragma unroll
+      for (int l = 0; l <= LM; ++l) sj = sj + (u[l] * R(iur[j * LUR + l])) * part[l];
+      acc = acc + widen(sj);
+    }
   }
   if constexpr (GRAD) {
     for (int a = 0; a < 3; ++a) out[3L * k + a] = (accumulate ? out[3L * k + a] : 0.0) + acc.g[a];
@@ -301,24 +328,27 @@ __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, c
 
 // Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
 // for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
-template <int LMO>
+// R = float (mixed path): each thread's running sums over its points are FP32, the
+// sums across threads FP64.
+template <int LMO, class R = double>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
                                                           const int* __restrict__ act_n, const double* __restrict__ xyz,
                                                           const double* __restrict__ rad, const double* __restrict__ leb,
                                                           const int* __restrict__ lptr, const int* __restrict__ lidx,
-                                                          const double* __restrict__ cgrid, const double* __restrict__ ur,
+                                                          const double* __restrict__ cgrid, const double* __restrict__ iur,
                                                           int LUR, double kappa, int exclude_self, int accumulate,
                                                           int LDL, double* __restrict__ lam) {
   constexpr int LO = (LMO + 1) * (LMO + 1);
   __shared__ double red[4 * LO];
   const int j = blockIdx.x;
-  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j], irj = 1.0 / rj;
+  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2], rj = rad[j];
+  const R irj = recip<R>(rj);
   // 1 / u_l(r_j) in LDS (registers go to the LO accumulators)
-  __shared__ double iu[LMO + 1];
-  if (threadIdx.x <= LMO) iu[threadIdx.x] = 1.0 / ur[j * LUR + threadIdx.x];
-  double acc[LO];
+  __shared__ R iu[LMO + 1];
+  if (threadIdx.x <= LMO) iu[threadIdx.x] = R(iur[j * LUR + threadIdx.x]);
+  R acc[LO];
 #pragma unroll
-  for (int t = 0; t < LO; ++t) acc[t] = 0.0;
+  for (int t = 0; t < LO; ++t) acc[t] = R(0);
   // the active points of up to kSlaSeg listed spheres are numbered consecutively
   // (prefix sums in LDS) so that every thread of the block has points to take
   constexpr int kSlaSeg = 128;
@@ -349,21 +379,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int n = act_n[k];
       const double c = cgrid[(long)i * N + n];
       if (c == 0.0) continue;
-      const double vx = (xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-      const double vy = (xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-      const double vz = (xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
-      const double rho = sqrt(vx * vx + vy * vy + vz * vz) * rj;
-      double u[LMO + 1];
-      k_weights<LMO, double>(rho, kappa, u);
+      const R vx = R(xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
+      const R vy = R(xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
+      const R vz = R(xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const R rho = dsqrt(vx * vx + vy * vy + vz * vz) * R(rj);
+      R u[LMO + 1];
+      k_weights<LMO, R>(rho, kappa, u);
 #pragma unroll
-      for (int l = 0; l <= LMO; ++l) u[l] *= c * iu[l];
-      for_each_solid_harmonic<LMO, double>(vx, vy, vz, [&](int l, int idx, double S) { acc[idx] += u[l] * S; });
+      for (int l = 0; l <= LMO; ++l) u[l] *= R(c) * iu[l];
+      for_each_solid_harmonic<LMO, R>(vx, vy, vz, [&](int l, int idx, R S) { acc[idx] += u[l] * S; });
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int t = 0; t < LO; ++t) {
-    double v = wave_sum(acc[t]);
+    double v = wave_sum((double)acc[t]);
     if (lane == 0) red[wid * LO + t] = v;
   }
   __syncthreads();
@@ -670,10 +700,6 @@ __global__ void k_mupdate(long D, int nv, const double* __restrict__ V, long ldv
   w[k] = s;
 }
 // y = a x + b y
-__global__ void k_scale(long D, double a, const double* __restrict__ x, double* __restrict__ y) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k < D) y[k] = a * x[k];
-}
 __global__ void k_axpby(long D, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (k < D) y[k] = a * x[k] + b * y[k];

@@ -63,3 +63,41 @@ def test_mixed_matches_fp64_fmm(precision):
     assert precision == 1 or st["refinements"] >= 2
     assert abs(Em / Ed - 1) < 1e-7
     assert _rel(Fm, Fd) < 1e-5
+
+
+def test_fp32_near_single_layer_is_single_precision():
+    """The operator of the mixed outer iterations (near single layer in FP32, FMM
+    p = 12) differs from the FP64 operator by single-precision rounding only."""
+    x, r, q = inputs.lattice_cluster(1500, seed=24)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    d = Context(x, r, q, **kw)
+    s = Context(x, r, q, options={"apply_fp32": 2}, **kw)
+    X = np.random.default_rng(1).normal(size=(2, len(r), 81))
+    for tr in (False, True):
+        e = _rel(s.apply(X, transpose=tr), d.apply(X, transpose=tr))
+        assert 1e-10 < e < 1e-5, (tr, e)
+
+
+def test_mixed_tolerance_is_met_in_fp64():
+    """Precision 1 with the FP32 near single layer (option mixed_near_sl) and the
+    FMM at tol 1e-6: the FP64 operator's residual of the returned solution meets the
+    tolerance (the outer FP64 check), and energy and forces stay within the
+    mixed-path bar of the FP64 path at the same tolerance."""
+    x, r, q = inputs.lattice_cluster(3000, seed=25)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    d = Context(x, r, q, **kw)
+    m = Context(x, r, q, precision=1, options={"mixed_near_sl": 1}, **kw)
+    Ed = d.solve(1e-6)
+    d.adjoint(1e-6)
+    Fd = d.forces()
+    Em = m.solve(1e-6)
+    g = m.rhs()
+    X, _ = m.solution(adjoint=False)
+    res = np.linalg.norm(g - d.apply(X)) / np.linalg.norm(g)
+    m.adjoint(1e-6)
+    Fm = m.forces()
+    st = m.stats()
+    assert st["resid_primal"] <= 1e-6 and st["resid_adjoint"] <= 1e-6
+    assert res <= 1e-6, res
+    assert abs(Em / Ed - 1) < 1e-5
+    assert _rel(Fm, Fd) < 1e-3
