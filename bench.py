@@ -292,7 +292,9 @@ def main():
         ms, nl, work = kt[name]
         achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         return {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "launches_per_step": nl / args.steps,
+                "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": measured_traffic(name, atoms) if args.precision == "fp64" else None,
+                "launches_per_step": nl / args.steps,
                 "ms_per_launch": ms / nl if nl else 0.0, "flops_per_launch": work / nl if nl else 0.0}
 
     name, (ms, nl, work) = tops[0]

@@ -589,11 +589,23 @@ inline double flops_sl_pair(int lm) { double L = (lm + 1.0) * (lm + 1.0); return
 inline double flops_cap_pair(int lm, int nterms) { double L = (lm + 1.0) * (lm + 1.0); return 7.0 * L + 6.0 * nterms + 8.0 * (lm + 1) + 30.0; }
 
 // out (R x C, ldo) = A (R x K, lda) B (K x C, ldb) + c0 base (base null: no term), FP64
-// matrix cores (k_gemm_f64): 16 S rows of A per block in LDS, S = 4, 2 or 1, the largest
-// whose chunk fits 80 KB (two blocks per compute unit)
+// matrix cores: k_gemm_f64_kc for a deep contraction into few columns (depth chunked),
+// else k_gemm_f64 with 16 S rows of A per block in LDS, S = 4, 2 or 1, the largest whose
+// chunk fits 80 KB (two blocks per compute unit)
 void gemm_f64(ddlpb_ctx* c, int R, int C, int K, const double* A, int lda, const double* B, int ldb,
               const double* base, double c0, double* out, int ldo) {
   if (R <= 0 || C <= 0) return;
+  if (C <= 16 * kGemmWaves && K > 128) {
+    // deep contraction into at most eight column tiles (the projection An): depth in
+    // chunks of 52, four strips per block (27 KB of LDS)
+    constexpr int S = 4, KC = 52;
+    const size_t lds = (size_t)16 * S * (KC + 1) * sizeof(double);
+    const dim3 grid((unsigned)((R + 16 * S - 1) / (16 * S))), block(64 * ((C + 15) / 16));
+    hipLaunchKernelGGL(k_gemm_f64_kc<S>, grid, block, lds, c->stream, R, C, K, KC, A, lda, B, ldb, base, c0, out,
+                       ldo);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   int S = 4;
   while (S > 1 && gemm_f64_lds(S, K) > 80 * 1024) S /= 2;
   const size_t lds = gemm_f64_lds(S, K);

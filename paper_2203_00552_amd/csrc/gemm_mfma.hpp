@@ -97,6 +97,73 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_gemm_f64(int R, int C, int 
   }
 }
 
+// The same product for C <= 16 kGemmWaves (one 16-column tile per wavefront) and a
+// deep contraction: the block walks the depth in chunks of KC (a multiple of 4), so that
+// its LDS chunk (16 S x (KC + 1) doubles) stays small and several blocks share a
+// compute unit; the accumulators persist across the chunks.
+template <int S>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_gemm_f64_kc(int R, int C, int K, int KC,
+                                                                 const double* __restrict__ A, int lda,
+                                                                 const double* __restrict__ B, int ldb,
+                                                                 const double* base, double c0, double* out,
+                                                                 int ldo) {
+  extern __shared__ double as[];
+  const int ap = KC + 1;
+  const long r0 = (long)blockIdx.x * (16 * S);
+  const int rows = (int)min((long)(16 * S), (long)R - r0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int col = 16 * w + i;
+  const bool cok = col < C;
+  dbl4 acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();  // the previous chunk is consumed
+    for (int rr = w; rr < 16 * S; rr += nw) {
+      const double* __restrict__ src = A + (r0 + rr) * lda + k0;
+      for (int kk = lane; kk < KC; kk += 64) as[rr * ap + kk] = (rr < rows && k0 + kk < K) ? src[kk] : 0.0;
+    }
+    __syncthreads();
+    const int ks = min(KC, K - k0 + 3) >> 2;  // steps of four in this chunk
+    double bq[kPf];
+#pragma unroll
+    for (int p = 0; p < kPf; ++p) {
+      const int kb = k0 + 4 * p + q;
+      bq[p] = (cok && p < ks && kb < K) ? B[(long)kb * ldb + col] : 0.0;
+    }
+    for (int kq = 0; kq < ks; kq += kPf) {
+#pragma unroll
+      for (int p = 0; p < kPf; ++p) {
+        const int k = kq + p;
+        if (k < ks) {
+          const double b = bq[p];
+          const int kb = k0 + 4 * (k + kPf) + q;
+          bq[p] = (cok && k + kPf < ks && kb < K) ? B[(long)kb * ldb + col] : 0.0;
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const double a = as[(16 * s + i) * ap + 4 * k + q];
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  if (cok) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = 16 * s + q + 4 * e;
+        if (rr < rows) {
+          const long o = (r0 + rr) * ldo + col;
+          out[o] = base ? fma(c0, base[o], acc[s][e]) : acc[s][e];
+        }
+      }
+    }
+  }
+}
+
 // LDS bytes of a launch with S strips per chunk
 inline size_t gemm_f64_lds(int S, int K) { return (size_t)16 * S * (4 * ((K + 3) / 4) + 1) * sizeof(double); }
 
