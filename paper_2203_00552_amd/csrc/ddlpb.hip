@@ -161,6 +161,7 @@ struct ddlpb_ctx {
   int *d_nptr = nullptr, *d_nidx = nullptr, *d_nrev = nullptr;
   double *d_f = nullptr, *d_U = nullptr;
   int *d_actcnt = nullptr, *d_actptr = nullptr, *d_actsph = nullptr, *d_actn = nullptr;
+  double* d_pt4 = nullptr;
   double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_iur = nullptr, *d_kr = nullptr;
   double *d_dtab = nullptr;
   double *d_rtab = nullptr;  // radius derivatives of the radial constants [4][M][LUR]
@@ -380,6 +381,7 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_actptr = cv.take<int>(M + 1);
   c->d_actsph = cv.take<int>(MN);
   c->d_actn = cv.take<int>(MN);
+  c->d_pt4 = cv.take<double>(4 * MN);  // active points and grid charges, packed [nact][4]
   c->d_ycr = cv.take<double>(M * c->LUR);
   c->d_yce = cv.take<double>(M * c->LUR);
   c->d_Cl = cv.take<double>(M * c->LUR);
@@ -805,12 +807,23 @@ void sl_field_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double*
   }
   HIPCHK(hipGetLastError());
 }
+// active points with this call's grid charges, packed for k_sl_adjoint_list
+const double4* pack_points(ddlpb_ctx* c, const double* cgrid) {
+  double4* pt = reinterpret_cast<double4*>(c->d_pt4);
+  if (c->nact > 0) {
+    hipLaunchKernelGGL(k_pack_points, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->nact, c->N, c->d_actsph,
+                       c->d_actn, c->d_xyz, c->d_rad, c->d_leb, cgrid, pt);
+    HIPCHK(hipGetLastError());
+  }
+  return pt;
+}
 void sl_adjoint_list(ddlpb_ctx* c, const int* lptr, const int* lidx, const double* cgrid, int lo, int exclude_self,
                      int accumulate, int ldl, double* lam) {
   KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pairs_pts);
-  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
-                                     c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, lptr, lidx, cgrid, c->d_iur,
-                                     c->LUR, c->kappa, exclude_self, accumulate, ldl, lam));
+  const double4* pt = pack_points(c, cgrid);
+  LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->d_actptr,
+                                     pt, c->d_xyz, c->d_rad, lptr, lidx, c->d_iur, c->LUR, c->kappa, exclude_self,
+                                     accumulate, ldl, lam));
   HIPCHK(hipGetLastError());
 }
 
@@ -1155,15 +1168,17 @@ void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self
   if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
   if (c->sl32 && lo == c->lmax) {
     KScope ks(c, "sl_near_adjoint_f32", flops_sl_pair(lo) * c->near_pts_fmm);
+    const double4* pt = pack_points(c, cgrid);
     LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc, float>), dim3(c->M), dim3(256), 0, c->stream, c->M,
-                                       c->N, c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni,
-                                       cgrid, c->d_iur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
+                                       c->d_actptr, pt, c->d_xyz, c->d_rad, c->d_fnp, c->d_fni, c->d_iur, c->LUR,
+                                       c->kappa, exclude_self, 0, ldl, lam));
     HIPCHK(hipGetLastError());
   } else {
     KScope ks(c, "sl_near_adjoint", flops_sl_pair(lo) * c->near_pts_fmm);
-    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N,
-                                       c->d_actptr, c->d_actn, c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, cgrid,
-                                       c->d_iur, c->LUR, c->kappa, exclude_self, 0, ldl, lam));
+    const double4* pt = pack_points(c, cgrid);
+    LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M,
+                                       c->d_actptr, pt, c->d_xyz, c->d_rad, c->d_fnp, c->d_fni, c->d_iur, c->LUR,
+                                       c->kappa, exclude_self, 0, ldl, lam));
     HIPCHK(hipGetLastError());
   }
   p2l_dual(c, cgrid, nullptr, c->d_Lam);

@@ -326,18 +326,32 @@ __global__ __launch_bounds__(256) void k_sl_field_list(int M, int N, int nact, c
   }
 }
 
+// Active grid points packed for the adjoint single layer: pt[k] = (x_i^n, c_in) of active
+// point k (sphere act_sph[k], point act_n[k]), c the grid charge of this call.
+__global__ void k_pack_points(int nact, int N, const int* __restrict__ act_sph, const int* __restrict__ act_n,
+                              const double* __restrict__ xyz, const double* __restrict__ rad,
+                              const double* __restrict__ leb, const double* __restrict__ cgrid,
+                              double4* __restrict__ pt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int i = act_sph[k], n = act_n[k];
+  const double r = rad[i];
+  pt[k] = make_double4(xyz[3 * i] + r * leb[4 * n], xyz[3 * i + 1] + r * leb[4 * n + 1],
+                       xyz[3 * i + 2] + r * leb[4 * n + 2], cgrid[(long)i * N + n]);
+}
+
 // Adjoint of k_sl_field_list: lambda_j = sum over the active points of the spheres listed
-// for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric).
+// for j of c_p k_l(kappa|x_p-x_j|)/k_l(kappa r_j) Y_lm (the lists are symmetric), with the
+// active points packed by k_pack_points (consecutive points of a sphere are consecutive
+// 32-byte records, and a point costs one load).
 // R = float (mixed path): each thread's running sums over its points are FP32, the
 // sums across threads FP64.
 template <int LMO, class R = double>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_sl_adjoint_list(int M, int N, const int* __restrict__ act_ptr,
-                                                          const int* __restrict__ act_n, const double* __restrict__ xyz,
-                                                          const double* __restrict__ rad, const double* __restrict__ leb,
-                                                          const int* __restrict__ lptr, const int* __restrict__ lidx,
-                                                          const double* __restrict__ cgrid, const double* __restrict__ iur,
-                                                          int LUR, double kappa, int exclude_self, int accumulate,
-                                                          int LDL, double* __restrict__ lam) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_sl_adjoint_list(
+    int M, const int* __restrict__ act_ptr, const double4* __restrict__ pt, const double* __restrict__ xyz,
+    const double* __restrict__ rad, const int* __restrict__ lptr, const int* __restrict__ lidx,
+    const double* __restrict__ iur, int LUR, double kappa, int exclude_self, int accumulate, int LDL,
+    double* __restrict__ lam) {
   constexpr int LO = (LMO + 1) * (LMO + 1);
   __shared__ double red[4 * LO];
   const int j = blockIdx.x;
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // the active points of up to kSlaSeg listed spheres are numbered consecutively
   // (prefix sums in LDS) so that every thread of the block has points to take
   constexpr int kSlaSeg = 128;
-  __shared__ int seg_sph[kSlaSeg], seg_pre[kSlaSeg + 1];
+  __shared__ int seg_base[kSlaSeg], seg_pre[kSlaSeg + 1];
   for (int q0 = lptr[j]; q0 < lptr[j + 1]; q0 += kSlaSeg) {
     const int ns = min(kSlaSeg, lptr[j + 1] - q0);
     __syncthreads();
@@ -360,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       int acc_n = 0;
       for (int u = 0; u < ns; ++u) {
         const int i = lidx[q0 + u];
-        seg_sph[u] = i;
+        seg_base[u] = act_ptr[i];
         seg_pre[u] = acc_n;
         acc_n += (exclude_self && i == j) ? 0 : act_ptr[i + 1] - act_ptr[i];
       }
@@ -374,19 +388,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int mid = (lo + hi + 1) >> 1;
         if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
       }
-      const int i = seg_sph[lo];
-      const int k = act_ptr[i] + (f - seg_pre[lo]);
-      const int n = act_n[k];
-      const double c = cgrid[(long)i * N + n];
-      if (c == 0.0) continue;
-      const R vx = R(xyz[3 * i] + rad[i] * leb[4 * n] - xj) * irj;
-      const R vy = R(xyz[3 * i + 1] + rad[i] * leb[4 * n + 1] - yj) * irj;
-      const R vz = R(xyz[3 * i + 2] + rad[i] * leb[4 * n + 2] - zj) * irj;
+      const double4 p = pt[seg_base[lo] + (f - seg_pre[lo])];
+      if (p.w == 0.0) continue;
+      const R vx = R(p.x - xj) * irj;
+      const R vy = R(p.y - yj) * irj;
+      const R vz = R(p.z - zj) * irj;
       const R rho = dsqrt(vx * vx + vy * vy + vz * vz) * R(rj);
       R u[LMO + 1];
       k_weights<LMO, R>(rho, kappa, u);
 #pragma unroll
-      for (int l = 0; l <= LMO; ++l) u[l] *= R(c) * iu[l];
+      for (int l = 0; l <= LMO; ++l) u[l] *= R(p.w) * iu[l];
       for_each_solid_harmonic<LMO, R>(vx, vy, vz, [&](int l, int idx, R S) { acc[idx] += u[l] * S; });
     }
   }
