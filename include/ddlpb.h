@@ -198,15 +198,16 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *   "precision"      0 = FP64 everywhere.
  *                    1 = mixed: the preconditioner (the Krylov steps on L_AB and
  *                    their Jacobi sweeps) runs the near-field A/B kernels in FP32;
- *                    flexible GMRES on the FP64 operator (FP64 residual, vectors,
- *                    orthogonalisation, norms) restores the tolerance.  With
- *                    option mixed_near_sl = 1 (and the FMM), the outer iterations
- *                    also apply the near single layer (the directly summed sphere
- *                    pairs of the C part) in FP32 (FP32 per pair, FP64 sums), and
- *                    then the FP64 operator's residual b - L x decides: flexible
- *                    GMRES continues on the FP64 operator from x until it meets
- *                    tol (stats.refinements counts those FP64 iterations of the
- *                    last solve).
+ *                    flexible GMRES (FP64 residual, vectors, orthogonalisation,
+ *                    norms) restores the tolerance.  With the FMM at order 12 the
+ *                    outer iterations run the multipole-to-local translations
+ *                    with an FP32 coefficient vector (option mixed_m2l), and with
+ *                    option mixed_near_sl = 1 the near single layer (the directly
+ *                    summed sphere pairs of the C part) in FP32 (FP32 per pair,
+ *                    FP64 sums); then the FP64 operator's residual b - L x
+ *                    decides: flexible GMRES continues on the FP64 operator from x
+ *                    until it meets tol (stats.refinements counts those FP64
+ *                    iterations of the last solve).
  *                    2 = mixed with FP32 operator: FP64 iterative refinement (FP64
  *                    residual b - L x) around GMRES solves of the correction
  *                    equation in which the near-field kernels (operator and
@@ -245,10 +246,21 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    0: every solve starts from zero
  *   "mixed_near_sl"  1: precision 1 with the FMM applies the near single layer
  *                    of the outer iterations in FP32 (see "precision"); 0 (default)
+ *   "mixed_m2l"      1 (default): precision 1 with the FMM at order 12 runs the
+ *                    screened Coulomb multipole-to-local translations of the outer
+ *                    iterations with an FP32 coefficient vector (rotations and
+ *                    reduction FP32; translation along z, degree scales and sums
+ *                    FP64), followed by the same FP64 residual check; 0: FP64
+ *   "mixed_forces"   1 (default): precision 1 with the FMM computes the single-layer
+ *                    terms of ddlpb_forces (near pairs of the field, its gradient
+ *                    and the transposed sums) with FP32 pairs and FP64 sums, and
+ *                    its order-12 screened Coulomb translations with the FP32
+ *                    vector; 0: FP64
  *   "apply_fp32"     1: ddlpb_apply uses the FP32 near-field A/B kernels of the
  *                    mixed preconditioner; 2: the FP32 near single layer of the
- *                    mixed outer iterations (FMM only); 0: FP64 (diagnostic:
- *                    operator error of the mixed path)
+ *                    mixed outer iterations (FMM only); 3: the FP32-vector
+ *                    multipole-to-local translations (FMM order 12); 0: FP64
+ *                    (diagnostic: operator error of the mixed path)
  *   "m2l_waves"      wavefronts per block of the wavefront multipole-to-local
  *                    kernel (0 = chosen from the occupancy calculator; 1, 2, 4,
  *                    8, 16; -1 = the one-node-per-block kernel built on the

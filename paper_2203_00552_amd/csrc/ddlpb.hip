@@ -115,12 +115,15 @@ struct ddlpb_ctx {
   int cur_prec = 0;           // compute type of the operator kernels now: 0 FP64, 1 FP32 (inner mixed solves)
   bool sl32 = false;          // near single layer of the operator in FP32 (outer iterations of precision 1)
   int fp64_iters = 0;         // FP64 outer iterations after the FP32 ones in the last solve (precision 1)
-  bool mixed_sl = false;      // precision 1: outer iterations with the FP32 near single layer (option mixed_near_sl)
+  bool mixed_sl = false;
+  bool m2l32 = false;         // screened Coulomb M2L with the FP32 vector (outer iterations of precision 1)
+  bool mixed_m2l = true;      // precision 1: outer iterations with the FP32-vector M2L (option mixed_m2l)
+  bool mixed_forces = true;   // precision 1: single-layer force terms with FP32 pairs and M2L (option mixed_forces)      // precision 1: outer iterations with the FP32 near single layer (option mixed_near_sl)
   double *d_rr = nullptr, *d_dd = nullptr;
   double* d_YT = nullptr;
   double* d_WY = nullptr;     // w_n Y_lm(s_n), [N][L] (column-major L x N): the An projection as a GEMM
   double* d_Vpt = nullptr;    // point values of the A/B sums, [2M][N], input of the An GEMM
-  int apply_fp32 = 0;         // ddlpb_apply: 1 FP32 near-field A/B kernels, 2 FP32 near single layer (diagnostic)
+  int apply_fp32 = 0;         // ddlpb_apply: 1 FP32 near-field A/B kernels, 2 FP32 near single layer, 3 FP32-vector M2L (diagnostic)
   int pkrylov = 6;            // > 0: preconditioner = this many GMRES steps on L_AB (flexible outer)
   int solver = 0;             // 0: GMRES, 1: Jacobi-DIIS (the paper's macro/micro iterations)
   int diis_max = 8;           // DIIS history length
@@ -967,6 +970,8 @@ int lane_tables_ready(const fmm::Tables& tb) {
     HIPCHK(lane12::upload_yt(J.data(), JT.data()));
     HIPCHK(lane12::upload_lf(J.data(), JT.data()));
     HIPCHK(lane12::upload_lt(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yf32(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yt32(J.data(), JT.data()));
     HIPCHK(lane12::upload_ym2m(J.data(), JT.data()));
     HIPCHK(lane12::upload_yl2l(J.data(), JT.data()));
     HIPCHK(lane12::upload_ym2mT(J.data(), JT.data()));
@@ -980,10 +985,12 @@ bool launch_m2l_lane(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* 
                      double* out) {
   if (f.p != lane12::kP || !c->m2l_lane || c->m2l_waves != 0) return false;
   if (lane_tables_ready(c->tables) < 0) return false;
-  const int which = (f.kernel == 0 ? 0 : 2) + (transposed ? 1 : 0);
+  // 4, 5: the FP32-vector screened Coulomb instances (mixed outer iterations)
+  const int which = (c->m2l32 && f.kernel == 0) ? 4 + (transposed ? 1 : 0)
+                                                : (f.kernel == 0 ? 0 : 2) + (transposed ? 1 : 0);
   int per_cu = 0, dev = 0, ncu = 0;
-  hipError_t (*occ[4])(int*) = {lane12::occupancy_yf, lane12::occupancy_yt, lane12::occupancy_lf,
-                                lane12::occupancy_lt};
+  hipError_t (*occ[6])(int*) = {lane12::occupancy_yf, lane12::occupancy_yt, lane12::occupancy_lf,
+                                lane12::occupancy_lt, lane12::occupancy_yf32, lane12::occupancy_yt32};
   HIPCHK(occ[which](&per_cu));
   if (per_cu < 1) return false;
   HIPCHK(hipGetDevice(&dev));
@@ -997,8 +1004,9 @@ bool launch_m2l_lane(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* 
   c->m2l_layout = 100 + which;
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->d_fctr, 1);
   HIPCHK(hipGetLastError());
-  hipError_t (*fn[4])(const FmmDev&, const lane12::LaneTab&, int, const int*, const int*, const double*, double*, int,
-                      hipStream_t) = {lane12::launch_yf, lane12::launch_yt, lane12::launch_lf, lane12::launch_lt};
+  hipError_t (*fn[6])(const FmmDev&, const lane12::LaneTab&, int, const int*, const int*, const double*, double*, int,
+                      hipStream_t) = {lane12::launch_yf,   lane12::launch_yt,   lane12::launch_lf,
+                                      lane12::launch_lt,   lane12::launch_yf32, lane12::launch_yt32};
   HIPCHK(fn[which](f, t, c->tree.nnodes, lptr, lidx, in, out, blocks, c->stream));
   return true;
 }
@@ -1006,7 +1014,9 @@ void launch_m2l(ddlpb_ctx* c, const FmmDev& f, const int* lptr, const int* lidx,
                 double* out) {
   const auto& t = c->tree;
   const auto& tb = c->tables;
-  KScope ks(c, f.kernel == 0 ? (transposed ? "m2l_yukawa_T" : "m2l_yukawa") : (transposed ? "m2l_laplace_T" : "m2l_laplace"),
+  const bool f32 = c->m2l32 && f.kernel == 0 && f.p == lane12::kP && c->m2l_lane && c->m2l_waves == 0;
+  KScope ks(c, f.kernel == 0 ? (transposed ? (f32 ? "m2l_yukawa_T_f32" : "m2l_yukawa_T") : (f32 ? "m2l_yukawa_f32" : "m2l_yukawa"))
+                             : (transposed ? "m2l_laplace_T" : "m2l_laplace"),
             flops_m2l_fast(f.kernel, f.p, tb.Jval.size()) * (double)t.m2l_src.size());
   if (launch_m2l_lane(c, f, lptr, lidx, transposed, in, out)) return;
   int nw, per_cu;
@@ -1166,7 +1176,7 @@ void sl_field_full(ddlpb_ctx* c, const double* m, double* Phi) {
 // lambda (degree lo, stride ldl) from grid charges: direct, or FMM near list + far field
 void sl_adjoint_full(ddlpb_ctx* c, const double* cgrid, int lo, int exclude_self, int ldl, double* lam) {
   if (c->fmm_order == 0) { sl_adjoint(c, cgrid, lo, exclude_self, lam); return; }
-  if (c->sl32 && lo == c->lmax) {
+  if (c->sl32) {
     KScope ks(c, "sl_near_adjoint_f32", flops_sl_pair(lo) * c->near_pts_fmm);
     const double4* pt = pack_points(c, cgrid);
     LM_DISPATCH(lo, hipLaunchKernelGGL((k_sl_adjoint_list<LMc, float>), dim3(c->M), dim3(256), 0, c->stream, c->M,
@@ -1382,7 +1392,7 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
       c->cur_prec = keep;
       c->inner_total += it;
     };
-    if (!fp32 || c->fmm_order == 0 || !c->mixed_sl)
+    if (!fp32 || c->fmm_order == 0 || !(c->mixed_sl || c->mixed_m2l))
       return gmres_core(c, opL, inner, b, x, tol, c->restart, c->maxit, 1 << 30, false, c->d_V, c->d_Z, c->d_w,
                         c->d_t1, c->d_t2, iters, relres);
     // mixed path with the FMM: the outer iterations apply the operator with its near
@@ -1391,8 +1401,14 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
     // FP64 outer refinement; usually the check alone)
     struct Sl32 {
       ddlpb_ctx* c;
-      explicit Sl32(ddlpb_ctx* cc) : c(cc) { c->sl32 = true; }
-      ~Sl32() { c->sl32 = false; }
+      explicit Sl32(ddlpb_ctx* cc) : c(cc) {
+        c->sl32 = c->mixed_sl;
+        c->m2l32 = c->mixed_m2l;
+      }
+      ~Sl32() {
+        c->sl32 = false;
+        c->m2l32 = false;
+      }
     };
     VecOp opLm = [&](const double* in, double* out) {
       Sl32 g(c);
@@ -1998,6 +2014,13 @@ void adjoint_fields(ddlpb_ctx* c) {
   // grad Phi' at active points (near part by pairs, far part from the sphere locals)
   if (!fmmode) {
     sl_field(c, c->d_m, true, 1, c->d_gphi);
+  } else if (c->sl32) {
+    KScope ks(c, "sl_near_grad_f32", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
+    LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true, float>), dim3(nblk(c->nact, 256)),
+                                            dim3(256), 0, c->stream, c->M, c->N, c->nact, c->d_actsph, c->d_actn,
+                                            c->d_xyz, c->d_rad, c->d_leb, c->d_fnp, c->d_fni, c->d_m, c->d_iur,
+                                            c->LUR, c->kappa, 1, 0, c->d_gphi));
+    HIPCHK(hipGetLastError());
   } else {
     KScope ks(c, "sl_near_grad", 4.0 * flops_sl_pair(c->lmax) * c->near_pts_fmm);
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_sl_field_list<LMc, true>), dim3(nblk(c->nact, 256)), dim3(256), 0,
@@ -2147,7 +2170,18 @@ int ddlpb_forces(ddlpb_ctx* c, double* forces_out) {
   return guarded([&]() -> int {
     auto t0 = std::chrono::steady_clock::now();
     const int M = c->M, N = c->N;
-    adjoint_fields(c);
+    {
+      // mixed path with the FMM: the single-layer terms of the force fields with FP32
+      // pairs (FP64 sums) and the FP32-vector M2L (option mixed_forces)
+      const bool f32 = c->precision == 1 && c->fmm_order > 0 && c->mixed_forces;
+      struct Flags {
+        ddlpb_ctx* c;
+        ~Flags() { c->sl32 = c->m2l32 = false; }
+      } restore{c};
+      c->sl32 = f32;
+      c->m2l32 = f32;
+      adjoint_fields(c);
+    }
     const bool fmmode = c->fmm_order > 0;
     // switching / near-field terms
     LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_force_switch<LMc>), dim3(M), dim3(256), 0, c->stream, M, N, c->d_leb,
@@ -2442,11 +2476,17 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 0 && v <= 64)) return DDLPB_EINVAL;
     c->pkrylov = (int)v;
+  } else if (k == "mixed_forces") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->mixed_forces = v != 0;
+  } else if (k == "mixed_m2l") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->mixed_m2l = v != 0;
   } else if (k == "mixed_near_sl") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_sl = v != 0;
   } else if (k == "apply_fp32") {
-    if (!(v == 0 || v == 1 || v == 2)) return DDLPB_EINVAL;
+    if (!(v >= 0 && v <= 3)) return DDLPB_EINVAL;
     c->apply_fp32 = (int)v;
   } else if (k == "m2l_waves") {
     if (!(v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16)) return DDLPB_EINVAL;
@@ -2694,15 +2734,16 @@ int ddlpb_apply(ddlpb_ctx* c, int32_t transpose, const double* x_in, double* y_o
     HIPCHK(hipMemcpyAsync(c->d_t2, x_in, D * sizeof(double), hipMemcpyHostToDevice, c->stream));
     c->cur_prec = c->apply_fp32 == 1 ? 1 : 0;
     c->sl32 = c->apply_fp32 == 2;
+    c->m2l32 = c->apply_fp32 == 3;
     try {
       if (transpose) op_LT(c, c->d_t2, c->d_w); else op_L(c, c->d_t2, c->d_w);
     } catch (...) {
       c->cur_prec = 0;
-      c->sl32 = false;
+      c->sl32 = c->m2l32 = false;
       throw;
     }
     c->cur_prec = 0;
-    c->sl32 = false;
+    c->sl32 = c->m2l32 = false;
     HIPCHK(hipMemcpyAsync(y_out, c->d_w, D * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return DDLPB_OK;

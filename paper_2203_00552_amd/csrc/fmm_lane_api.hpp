@@ -76,6 +76,9 @@ DDLPB_M2L_LANE_DECL(yf)
 DDLPB_M2L_LANE_DECL(yt)
 DDLPB_M2L_LANE_DECL(lf)
 DDLPB_M2L_LANE_DECL(lt)
+// FP32-vector instances of the screened Coulomb kernel (fmm_lane32.hpp): yf32, yt32
+DDLPB_M2L_LANE_DECL(yf32)
+DDLPB_M2L_LANE_DECL(yt32)
 #undef DDLPB_M2L_LANE_DECL
 
 // Level translations of the screened Coulomb expansions (fmm_lane_level.hpp), one node

@@ -86,7 +86,44 @@ def test_mixed_tolerance_is_met_in_fp64():
     x, r, q = inputs.lattice_cluster(3000, seed=25)
     kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
     d = Context(x, r, q, **kw)
-    m = Context(x, r, q, precision=1, options={"mixed_near_sl": 1}, **kw)
+    m = Context(x, r, q, precision=1, options={"mixed_near_sl": 1, "mixed_m2l": 0}, **kw)
+    Ed = d.solve(1e-6)
+    d.adjoint(1e-6)
+    Fd = d.forces()
+    Em = m.solve(1e-6)
+    g = m.rhs()
+    X, _ = m.solution(adjoint=False)
+    res = np.linalg.norm(g - d.apply(X)) / np.linalg.norm(g)
+    m.adjoint(1e-6)
+    Fm = m.forces()
+    st = m.stats()
+    assert st["resid_primal"] <= 1e-6 and st["resid_adjoint"] <= 1e-6
+    assert res <= 1e-6, res
+    assert abs(Em / Ed - 1) < 1e-5
+    assert _rel(Fm, Fd) < 1e-3
+
+
+def test_fp32_m2l_is_single_precision():
+    """The screened Coulomb M2L with the FP32 coefficient vector (FMM p = 12) changes the
+    operator by single-precision rounding only, in both directions."""
+    x, r, q = inputs.lattice_cluster(1500, seed=26)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    d = Context(x, r, q, **kw)
+    s = Context(x, r, q, options={"apply_fp32": 3}, **kw)
+    X = np.random.default_rng(2).normal(size=(2, len(r), 81))
+    for tr in (False, True):
+        e = _rel(s.apply(X, transpose=tr), d.apply(X, transpose=tr))
+        assert 1e-10 < e < 1e-5, (tr, e)
+
+
+def test_mixed_m2l_meets_tolerance_in_fp64():
+    """Precision 1 with the FP32-vector M2L (option mixed_m2l) at tol 1e-6: the FP64
+    operator's residual of the returned primal solution meets tol; energy and forces
+    stay within the mixed-path bar of the FP64 path at the same tolerance."""
+    x, r, q = inputs.lattice_cluster(3000, seed=27)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    d = Context(x, r, q, **kw)
+    m = Context(x, r, q, precision=1, options={"mixed_m2l": 1}, **kw)
     Ed = d.solve(1e-6)
     d.adjoint(1e-6)
     Fd = d.forces()
