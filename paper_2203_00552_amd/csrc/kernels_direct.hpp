@@ -382,13 +382,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     __syncthreads();
     const int total = seg_pre[ns];
-    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+    // record of point f (position, grid charge): binary search for its sphere in LDS
+    auto fetch = [&](int f) {
       int lo = 0, hi = ns - 1;  // last u with seg_pre[u] <= f
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (seg_pre[mid] <= f) lo = mid; else hi = mid - 1;
       }
-      const double4 p = pt[seg_base[lo] + (f - seg_pre[lo])];
+      return pt[seg_base[lo] + (f - seg_pre[lo])];
+    };
+    // the next point's record is loaded before the current point is evaluated
+    double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
+    if ((int)threadIdx.x < total) pn = fetch(threadIdx.x);
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+      const double4 p = pn;
+      if (f + (int)blockDim.x < total) pn = fetch(f + blockDim.x);
       if (p.w == 0.0) continue;
       const R vx = R(p.x - xj) * irj;
       const R vy = R(p.y - yj) * irj;
