@@ -251,6 +251,10 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    iterations with an FP32 coefficient vector (rotations and
  *                    reduction FP32; translation along z, degree scales and sums
  *                    FP64), followed by the same FP64 residual check; 0: FP64
+ *   "cap_lists"      1 (default): the A/B couplings walk per-sphere cap lists (the
+ *                    neighbour points inside each sphere) when they fit the
+ *                    workspace estimate; 0: always the kernels that find the caps
+ *                    on the fly from the neighbour lists (the fallback; FP64 only)
  *   "mixed_forces"   1 (default): precision 1 with the FMM computes the single-layer
  *                    terms of ddlpb_forces (near pairs of the field, its gradient
  *                    and the transposed sums) with FP32 pairs and FP64 sums, and

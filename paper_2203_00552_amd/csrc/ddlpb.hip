@@ -153,6 +153,7 @@ struct ddlpb_ctx {
   size_t nnz_cap = 0, pnz_cap = 0;  // capacities of the device copies of nidx / pidx
   size_t cap_est = 0, cap_cap = 0;  // estimated cap pairs and the capacity of the cap lists
   bool use_caps = false;            // cap lists built for the current geometry
+  bool cap_lists = true;            // option cap_lists: 0 forces the kernels without cap lists
   int nterms = 8, nterms_p = 8;
   // ---- device
   hipStream_t stream = nullptr;
@@ -1911,7 +1912,7 @@ void geometry_on_device(ddlpb_ctx* c) {
     size_t need = 0;
     LM_DISPATCH(c->lmax, need = std::max(k_apply_LX_caps_lds_entries<LMc>(N), k_apply_LTZ_caps_lds_entries<LMc>(N)) *
                                 sizeof(double));
-    c->use_caps = (size_t)c->ncap <= c->cap_cap && need <= (size_t)maxlds;
+    c->use_caps = c->cap_lists && (size_t)c->ncap <= c->cap_cap && need <= (size_t)maxlds;
   }
   if (c->use_caps) {
     std::vector<int> cp(M + 1, 0);
@@ -2476,6 +2477,10 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
     if (fixed) return DDLPB_ESTATE;
     if (!(v >= 0 && v <= 64)) return DDLPB_EINVAL;
     c->pkrylov = (int)v;
+  } else if (k == "cap_lists") {
+    if (fixed) return DDLPB_ESTATE;
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->cap_lists = v != 0;
   } else if (k == "mixed_forces") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_forces = v != 0;

@@ -122,3 +122,36 @@ def test_charge_gradient_config1(seed):
     ref = P.charge_gradient("dense")
     assert np.abs(g - ref).max() < 1e-8 * np.abs(ref).max()
     assert abs((q * g).sum() / (2 * E) - 1) < 1e-9
+
+
+@pytest.mark.parametrize("case", ["config1", "lattice40", "dense48"])
+def test_kernels_without_cap_lists_vs_oracle(case):
+    """The A/B kernels that find the caps on the fly from the neighbour lists (the
+    fallback when the cap lists do not fit; option cap_lists = 0) against the oracle:
+    operator images to rounding (also with more than 16 neighbours per sphere), energy
+    and forces to 1e-8."""
+    if case == "config1":
+        x, r, q = inputs.small_cluster(0)
+        lmax, npts = 6, 110
+    elif case == "lattice40":
+        x, r, q = inputs.lattice_cluster(40, seed=3)
+        lmax, npts = 8, 302
+    else:
+        x, r, q = inputs.lattice_cluster(48, seed=2, spacing=1.5)
+        lmax, npts = 8, 302
+    ctx, P = _pair(x, r, q, lmax, npts, options={"cap_lists": 0})
+    rng = np.random.default_rng(13)
+    X = rng.normal(size=(2, P.M, P.L))
+    for tr in (False, True):
+        Y = ctx.apply(X, transpose=tr)
+        Yo = P.apply(X, transpose=tr)
+        assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max(), tr
+    assert ctx.stats()["n_cap_pairs"] > 0
+    if case == "dense48":
+        return
+    E = ctx.solve(TOL)
+    ctx.adjoint(TOL)
+    F = ctx.forces()
+    ref = P.solve("dense" if case == "config1" else "gmres", tol=TOL)
+    assert abs(E / ref["energy"] - 1) < 1e-8
+    assert _relF(F, ref["forces"]) < 1e-8
