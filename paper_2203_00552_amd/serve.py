@@ -186,16 +186,23 @@ def run_poisson(server: Server, requests, rate, seed=0):
 
 
 def latency_summary(results, makespan, offered_atoms=None, arrival_span=None):
-    """p50/p99 latency and throughput of the served requests (entries of `results`
-    that are exceptions count as rejected); offered load when the requested atoms and
-    the arrival span are given."""
+    """p50/p99 latency (submission to completion), the same of the time on the device
+    (admission to completion) and the median queueing time, and the throughput of the
+    served requests (entries of `results` that are exceptions count as rejected);
+    offered load when the requested atoms and the arrival span are given."""
     ok = [r for r in results if isinstance(r, Result)]
     rejected = [(k, str(r)) for k, r in enumerate(results) if not isinstance(r, Result)]
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    # time on the device (admission to completion) and time queued before admission
+    svc = np.array([r.t_done - r.t_admit for r in ok]) if ok else np.zeros(1)
+    wait = np.array([r.t_admit - r.t_submit for r in ok]) if ok else np.zeros(1)
     atoms = sum(r.atoms for r in ok)
     conv_atoms = sum(r.atoms for r in ok if r.converged)
     out = {"requests": len(results), "served": len(ok), "rejected": len(rejected),
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "service_p50_ms": float(np.percentile(svc, 50) * 1e3),
+           "service_p99_ms": float(np.percentile(svc, 99) * 1e3),
+           "queue_p50_ms": float(np.percentile(wait, 50) * 1e3),
            "atoms_per_s": atoms / makespan if makespan > 0 else 0.0,
            "converged_atoms_per_s": conv_atoms / makespan if makespan > 0 else 0.0,
            "makespan_s": makespan, "atoms": atoms,

@@ -91,3 +91,11 @@ def test_latency_summary():
     rs = [serve.Result(k, 10, 0.0, None, 0.0, 0.0, 0.01 * (k + 1), 0, (1, 1)) for k in range(100)]
     summ = serve.latency_summary(rs, 1.0)
     assert abs(summ["p50_ms"] - 505.0) < 1e-6 and summ["atoms_per_s"] == 1000.0
+
+
+def test_latency_summary_splits_queue_and_service():
+    # submitted at 0, admitted at 0.1 k, done 0.05 after admission
+    rs = [serve.Result(k, 10, 0.0, None, 0.0, 0.1 * k, 0.1 * k + 0.05, 0, (1, 1)) for k in range(11)]
+    summ = serve.latency_summary(rs, 2.0)
+    assert abs(summ["service_p50_ms"] - 50.0) < 1e-9 and abs(summ["service_p99_ms"] - 50.0) < 1e-9
+    assert abs(summ["queue_p50_ms"] - 500.0) < 1e-9 and abs(summ["p50_ms"] - 550.0) < 1e-9
