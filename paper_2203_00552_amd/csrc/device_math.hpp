@@ -157,15 +157,20 @@ __device__ __forceinline__ void solid_harmonic_quad(R x, R y, R z, int q, const 
 
 // ------------------------------------------------------ Bessel weights
 // u_l = k_l(kappa rho) / rho^l for l = 0..LM (k_l = sqrt(pi/(2z)) K_{l+1/2}(z)).
+// One division per call: with ir = 1/rho, u_0 = (pi/2) e^{-z} ir / kappa and
+// u_1 = (pi/2) e^{-z} (z + 1) ir^3 / kappa^2 (z = kappa rho).
 template <int LM, class T>
 __device__ __forceinline__ void k_weights(const T& rho, double kappa, T* u) {
   using R = typename ScalarOf<T>::type;
   const R halfpi = R(1.5707963267948966);
+  const R ik = R(1.0 / kappa);
+  const T ir = T(R(1)) / rho;
   T z = R(kappa) * rho;
   T e = dexp(T(R(0)) - z);
-  u[0] = halfpi * (e / z);
-  if (LM >= 1) u[1] = halfpi * (e * (z + T(R(1)))) / (z * z * rho);
-  T ir2 = T(R(1)) / (rho * rho);
+  const T eh = halfpi * (e * ir);
+  u[0] = ik * eh;
+  T ir2 = ir * ir;
+  if (LM >= 1) u[1] = (ik * ik) * ((eh * (z + T(R(1)))) * ir2);
 #pragma unroll
   for (int l = 1; l < LM; ++l) u[l + 1] = (u[l - 1] + R((2.0 * l + 1.0) / kappa) * u[l]) * ir2;
 }
