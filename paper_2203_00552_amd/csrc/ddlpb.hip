@@ -266,7 +266,10 @@ int build_neighbours(ddlpb_ctx* c) {
     cells[key(ci[3L * i], ci[3L * i + 1], ci[3L * i + 2])].push_back(i);
   }
   std::vector<std::vector<int>> nb(M);
-  for (int i = 0; i < M; ++i) {
+  std::atomic<bool> coincident{false};
+  // sphere by sphere on the host threads (each list is sorted, so the result does not
+  // depend on the schedule)
+  fmm::parallel_for(M, 512, [&](long i) {
     for (long dx = -1; dx <= 1; ++dx)
       for (long dy = -1; dy <= 1; ++dy)
         for (long dz = -1; dz <= 1; ++dz) {
@@ -277,12 +280,13 @@ int build_neighbours(ddlpb_ctx* c) {
             double d2 = 0;
             for (int a = 0; a < 3; ++a) { double t = c->x[3 * i + a] - c->x[3 * j + a]; d2 += t * t; }
             double d = std::sqrt(d2);
-            if (d < 1e-12) return DDLPB_EGEOM;
+            if (d < 1e-12) coincident.store(true, std::memory_order_relaxed);
             if (d < c->r[i] + c->r[j]) nb[i].push_back(j);
           }
         }
     std::sort(nb[i].begin(), nb[i].end());
-  }
+  });
+  if (coincident.load()) return DDLPB_EGEOM;
   c->nptr.assign(M + 1, 0);
   for (int i = 0; i < M; ++i) c->nptr[i + 1] = c->nptr[i] + (int)nb[i].size();
   // cap pairs: the fraction of sphere i's surface inside ball j is (1 - c0)/2 with
@@ -313,6 +317,11 @@ int build_neighbours(ddlpb_ctx* c) {
 // Sphere pairs (i, j) with |x_i - x_j| < r_i + r_j + delta, i itself included, sorted by j.
 void build_pairs(const ddlpb_ctx* c, double delta, std::vector<int>& ptr, std::vector<int>& idx) {
   const int M = c->M;
+  if (delta < 0.0) {  // no two-level preconditioner: no pairs
+    ptr.assign(M + 1, 0);
+    idx.clear();
+    return;
+  }
   double rmax = 0;
   for (double v : c->r) rmax = std::max(rmax, v);
   const double cell = 2.0 * rmax + std::max(delta, 0.0);
@@ -2547,12 +2556,15 @@ int ddlpb_update_centers(ddlpb_ctx* c, const double* centers) {
     // previous geometry, restored when the new one cannot be set up (EGEOM, ENOMEM)
     const std::vector<double> old = c->x;
     const std::vector<int> onptr = c->nptr, onidx = c->nidx, onrev = c->nrev, opptr = c->pptr, opidx = c->pidx;
-    const fmm::Tree otree = c->tree;
+    // the old tree is moved aside (not copied) when a new one is built
+    fmm::Tree otree;
+    if (c->fmm_order > 0) otree = std::move(c->tree);
     const size_t ocap_est = c->cap_est, onnz = c->nnz_cap, opnz = c->pnz_cap, ocap = c->cap_cap, om2l = c->m2l_cap,
                  onear = c->near_cap;
     auto restore = [&]() {
       c->x = old; c->nptr = onptr; c->nidx = onidx; c->nrev = onrev; c->pptr = opptr; c->pidx = opidx;
-      c->tree = otree; c->cap_est = ocap_est; c->nnz_cap = onnz; c->pnz_cap = opnz; c->cap_cap = ocap;
+      if (c->fmm_order > 0) c->tree = std::move(otree);
+      c->cap_est = ocap_est; c->nnz_cap = onnz; c->pnz_cap = opnz; c->cap_cap = ocap;
       c->m2l_cap = om2l; c->near_cap = onear;
     };
     c->x.assign(centers, centers + 3L * c->M);
