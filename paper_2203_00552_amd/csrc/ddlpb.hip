@@ -1158,6 +1158,12 @@ void l2p(ddlpb_ctx* c, int mode, double c2, double* out1, double* out2) {
 }
 void p2l_dual(ddlpb_ctx* c, const double* g1, const double* g2, double* Lam) {
   const int P = (c->fmm_order + 1) * (c->fmm_order + 1);
+  if (!g2) {
+    // Lam [M][P] = g1 [M][N] x Y [N][P]: a dense product against the harmonic table,
+    // on the FP64 matrix cores
+    gemm_f64(c, c->M, P, c->N, g1, c->N, c->d_Y, c->LY, nullptr, 0.0, Lam, P);
+    return;
+  }
   hipLaunchKernelGGL(k_p2l_dual, dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, P, c->LY, c->d_rad, c->d_Y, g1, g2,
                      Lam);
   HIPCHK(hipGetLastError());
