@@ -100,3 +100,24 @@ def test_workspace_grows_with_krylov_preconditioner_depth():
     for a, b in ((16, 32), (32, 64)):
         # (b - a) more inner basis vectors and (b - a) more rows of 1024 partial dot products
         assert sizes[b] - sizes[a] >= (b - a) * (D * 8 + 1024 * 8) - 2 * 256
+
+
+def test_precision_and_kernel_options_are_validated():
+    """The mixed-precision and kernel-choice options accept exactly their documented
+    values (host-side checks, no device needed)."""
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0]])
+    r = np.array([1.5, 1.5])
+    q = np.array([0.5, -0.5])
+    assert lib.ddlpb_setup(2, _lib.ptr(x), _lib.ptr(r), _lib.ptr(q), 1.0, 78.54, 0.104, 4, 110, 0, ctypes.byref(h)) == 0
+    for key in (b"mixed_m2l", b"mixed_forces", b"mixed_near_sl", b"cap_lists"):
+        assert lib.ddlpb_set_option(h, key, 0) == 0, key
+        assert lib.ddlpb_set_option(h, key, 1) == 0, key
+        assert lib.ddlpb_set_option(h, key, 2) == -1, key
+        assert lib.ddlpb_set_option(h, key, 0.5) == -1, key
+    for v in (0, 1, 2, 3):
+        assert lib.ddlpb_set_option(h, b"apply_fp32", v) == 0
+    assert lib.ddlpb_set_option(h, b"apply_fp32", 4) == -1
+    assert lib.ddlpb_set_option(h, b"apply_fp32", -1) == -1
+    lib.ddlpb_free(h)
