@@ -255,6 +255,10 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    neighbour points inside each sphere) when they fit the
  *                    workspace estimate; 0: always the kernels that find the caps
  *                    on the fly from the neighbour lists (the fallback; FP64 only)
+ *   "mixed_levels"   1: where the FP32-vector M2L runs (mixed_m2l, mixed_forces),
+ *                    the order-12 screened Coulomb M2M/L2L level translations run
+ *                    with the FP32 vector as well; 0 (default: they cost the mixed
+ *                    adjoint more iterations than they save)
  *   "mixed_forces"   1 (default): precision 1 with the FMM computes the single-layer
  *                    terms of ddlpb_forces (near pairs of the field, its gradient
  *                    and the transposed sums) with FP32 pairs and FP64 sums, and

@@ -9,7 +9,8 @@ LIB = os.path.join(HERE, "libddlpb.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("ddlpb.hip", "near_lane.hip", "m2l_lane_yf.hip", "m2l_lane_yt.hip", "m2l_lane_lf.hip", "m2l_lane_lt.hip",
             "m2l_lane_yf32.hip", "m2l_lane_yt32.hip",
-            "level_lane_ym2m.hip", "level_lane_yl2l.hip", "level_lane_ym2mT.hip", "level_lane_yl2lT.hip")]
+            "level_lane_ym2m.hip", "level_lane_yl2l.hip", "level_lane_ym2mT.hip", "level_lane_yl2lT.hip",
+            "level_lane_ym2m32.hip", "level_lane_yl2l32.hip", "level_lane_ym2mT32.hip", "level_lane_yl2lT32.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-pthread"]

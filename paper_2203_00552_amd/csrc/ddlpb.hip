@@ -116,7 +116,8 @@ struct ddlpb_ctx {
   bool sl32 = false;          // near single layer of the operator in FP32 (outer iterations of precision 1)
   int fp64_iters = 0;         // FP64 outer iterations after the FP32 ones in the last solve (precision 1)
   bool mixed_sl = false;
-  bool m2l32 = false;         // screened Coulomb M2L with the FP32 vector (outer iterations of precision 1)
+  bool m2l32 = false;         // screened Coulomb M2L with the FP32 vector (precision 1; level passes too with mixed_lvl)
+  bool mixed_lvl = false;     // option mixed_levels: the order-12 level translations of the FP32 passes in FP32 too
   bool mixed_m2l = true;      // precision 1: outer iterations with the FP32-vector M2L (option mixed_m2l)
   bool mixed_forces = true;   // precision 1: single-layer force terms with FP32 pairs and M2L (option mixed_forces)      // precision 1: outer iterations with the FP32 near single layer (option mixed_near_sl)
   double *d_rr = nullptr, *d_dd = nullptr;
@@ -986,6 +987,10 @@ int lane_tables_ready(const fmm::Tables& tb) {
     HIPCHK(lane12::upload_yl2l(J.data(), JT.data()));
     HIPCHK(lane12::upload_ym2mT(J.data(), JT.data()));
     HIPCHK(lane12::upload_yl2lT(J.data(), JT.data()));
+    HIPCHK(lane12::upload_ym2m32(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yl2l32(J.data(), JT.data()));
+    HIPCHK(lane12::upload_ym2mT32(J.data(), JT.data()));
+    HIPCHK(lane12::upload_yl2lT32(J.data(), JT.data()));
   }
   g_lane_state[dev] = state;
   return state;
@@ -1094,11 +1099,15 @@ void run_level(ddlpb_ctx* c, const FmmDev& f, int which, int lev, int stage, siz
   const int* nodes = c->d_flevn + t.level_ptr[lev];
   if (f.kernel == 0 && f.p == lane12::kP && c->level_lane > 0 && cnt >= c->level_lane &&
       (int)c->tables.Zlvl[0].size() == lane12::kZYn && lane_tables_ready(c->tables) > 0) {
-    KScope ks(c, "level_lane", flops_translation(f.p) * ntr);
-    hipError_t (*fn[4])(const FmmDev&, const double*, int, const int*, const int*, const int*, double*,
-                        hipStream_t) = {lane12::launch_ym2m, lane12::launch_yl2l, lane12::launch_ym2mT,
-                                        lane12::launch_yl2lT};
-    HIPCHK(fn[which](f, c->d_fZl[which >= 2 ? 1 : 0], cnt, nodes, c->d_fchild, c->d_fparent, E, c->stream));
+    const bool f32 = c->m2l32 && c->mixed_lvl;
+    KScope ks(c, f32 ? "level_lane_f32" : "level_lane", flops_translation(f.p) * ntr);
+    hipError_t (*fn[8])(const FmmDev&, const double*, int, const int*, const int*, const int*, double*,
+                        hipStream_t) = {lane12::launch_ym2m,   lane12::launch_yl2l,   lane12::launch_ym2mT,
+                                        lane12::launch_yl2lT,  lane12::launch_ym2m32, lane12::launch_yl2l32,
+                                        lane12::launch_ym2mT32, lane12::launch_yl2lT32};
+    // 4..7: the FP32-vector instances (outer iterations of the mixed path)
+    HIPCHK(fn[which + (f32 ? 4 : 0)](f, c->d_fZl[which >= 2 ? 1 : 0], cnt, nodes, c->d_fchild, c->d_fparent,
+                                          E, c->stream));
     return;
   }
   KScope ks(c, "level_generic", flops_translation(f.p) * ntr);
@@ -2499,6 +2508,9 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "mixed_forces") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_forces = v != 0;
+  } else if (k == "mixed_levels") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->mixed_lvl = v != 0;
   } else if (k == "mixed_m2l") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_m2l = v != 0;

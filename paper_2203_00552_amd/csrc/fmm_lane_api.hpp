@@ -93,6 +93,11 @@ DDLPB_LEVEL_LANE_DECL(ym2m)
 DDLPB_LEVEL_LANE_DECL(yl2l)
 DDLPB_LEVEL_LANE_DECL(ym2mT)
 DDLPB_LEVEL_LANE_DECL(yl2lT)
+// FP32-vector instances (fmm_lane_level32.hpp)
+DDLPB_LEVEL_LANE_DECL(ym2m32)
+DDLPB_LEVEL_LANE_DECL(yl2l32)
+DDLPB_LEVEL_LANE_DECL(ym2mT32)
+DDLPB_LEVEL_LANE_DECL(yl2lT32)
 #undef DDLPB_LEVEL_LANE_DECL
 
 }  // namespace lane12

@@ -138,3 +138,17 @@ def test_mixed_m2l_meets_tolerance_in_fp64():
     assert res <= 1e-6, res
     assert abs(Em / Ed - 1) < 1e-5
     assert _rel(Fm, Fd) < 1e-3
+
+
+def test_fp32_level_translations_are_single_precision():
+    """With option mixed_levels the order-12 M2M/L2L level translations run with the
+    FP32 vector as well (levels of >= 1024 nodes, 3,000 atoms): the operator still
+    differs from FP64 by single-precision rounding only, in both directions."""
+    x, r, q = inputs.lattice_cluster(3000, seed=28)
+    kw = dict(lmax=8, n_lebedev=302, fmm_order=12)
+    d = Context(x, r, q, **kw)
+    s = Context(x, r, q, options={"apply_fp32": 3, "mixed_levels": 1}, **kw)
+    X = np.random.default_rng(3).normal(size=(2, len(r), 81))
+    for tr in (False, True):
+        e = _rel(s.apply(X, transpose=tr), d.apply(X, transpose=tr))
+        assert 1e-10 < e < 1e-5, (tr, e)
