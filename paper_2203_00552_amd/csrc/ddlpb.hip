@@ -1248,17 +1248,25 @@ void op_LT(ddlpb_ctx* c, const double* x, double* y) {
   apply_LTZ(c, x, 1.0, c->d_zr, c->d_ze, -1.0, c->d_lam, c->L, y);
 }
 // z = P^-1 v: k Jacobi sweeps z <- v + (I - L_AB) z from z = v (or the transposed sweeps)
+// The sweeps alternate between z and the scratch vector d_t3 so that the last one
+// lands in z; the first reads v itself (z = v before it), so no copies are made.
 void precond(ddlpb_ctx* c, bool transpose, const double* v, double* z) {
   const long D = 2L * c->M * c->L;
-  HIPCHK(hipMemcpyAsync(z, v, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  for (int s = 0; s < c->sweeps; ++s) {
+  const int k = c->sweeps;
+  if (k == 0) {
+    HIPCHK(hipMemcpyAsync(z, v, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return;
+  }
+  const double* in = v;
+  for (int s = 0; s < k; ++s) {
+    double* out = ((k - 1 - s) % 2 == 0) ? z : c->d_t3;
     if (!transpose) {
-      apply_LX(c, v, 1.0, z, 1.0, nullptr, nullptr, nullptr, 0.0, c->d_t3);
+      apply_LX(c, v, 1.0, in, 1.0, nullptr, nullptr, nullptr, 0.0, out);
     } else {
-      syn2(c, z, 0, c->d_zr, c->d_ze);
-      apply_LTZ(c, v, 1.0, c->d_zr, c->d_ze, 1.0, nullptr, 0, c->d_t3);
+      syn2(c, in, 0, c->d_zr, c->d_ze);
+      apply_LTZ(c, v, 1.0, c->d_zr, c->d_ze, 1.0, nullptr, 0, out);
     }
-    HIPCHK(hipMemcpyAsync(z, c->d_t3, D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    in = out;
   }
 }
 
