@@ -1161,6 +1161,15 @@ void fmm_transpose(ddlpb_ctx* c, int kernel, const double* Lam, int pd, int ldd,
 void l2p(ddlpb_ctx* c, int mode, double c2, double* out1, double* out2) {
   if (c->nact == 0) return;
   const int P = (c->fmm_order + 1) * (c->fmm_order + 1);
+  if (mode == 0) {
+    // the sphere locals at every grid point, [M][N] = SL [M][P] x YT [P][N], on the matrix
+    // cores into the point-value scratch, then added at the active points
+    const long MN = (long)c->M * c->N;
+    gemm_f64(c, c->M, c->N, P, c->d_SL, P, c->d_YT, c->N, nullptr, 0.0, c->d_Vpt, c->N);
+    hipLaunchKernelGGL(k_add_active, dim3(nblk(MN, 256)), dim3(256), 0, c->stream, MN, c->d_U, c->d_Vpt, out1);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(k_l2p, dim3(nblk(c->nact, 256)), dim3(256), 0, c->stream, c->nact, c->N, P, c->LY, c->d_actsph,
                      c->d_actn, c->d_rad, c->d_YT, c->d_SL, mode, c2, out1, out2);
   HIPCHK(hipGetLastError());
@@ -1242,9 +1251,13 @@ void op_L(ddlpb_ctx* c, const double* x, double* y) {
 }
 // y = L^T x
 void op_LT(ddlpb_ctx* c, const double* x, double* y) {
-  syn2(c, x, 1, c->d_cg, nullptr);
-  sl_adjoint_full(c, c->d_cg, c->lmax, 0, c->L, c->d_lam);
+  // one synthesis of x serves both the grid charges of the single layer and the A/B part
   syn2(c, x, 0, c->d_zr, c->d_ze);
+  const long MN = (long)c->M * c->N;
+  hipLaunchKernelGGL(k_charges_from_syn, dim3(nblk(MN, 256)), dim3(256), 0, c->stream, MN, c->N, c->d_leb, c->d_U,
+                     c->d_zr, c->d_ze, c->d_cg);
+  HIPCHK(hipGetLastError());
+  sl_adjoint_full(c, c->d_cg, c->lmax, 0, c->L, c->d_lam);
   apply_LTZ(c, x, 1.0, c->d_zr, c->d_ze, -1.0, c->d_lam, c->L, y);
 }
 // z = P^-1 v: k Jacobi sweeps z <- v + (I - L_AB) z from z = v (or the transposed sweeps)

@@ -718,6 +718,22 @@ __global__ void k_mupdate(long D, int nv, const double* __restrict__ V, long ldv
   for (int v = 0; v < nv; ++v) s -= V[v * ldv + k] * h[v];
   w[k] = s;
 }
+// adjoint grid charges from the two syntheses: c_in = w_n U_in (zr_in + ze_in)
+__global__ void k_charges_from_syn(long MN, int N, const double* __restrict__ leb, const double* __restrict__ U,
+                                   const double* __restrict__ zr, const double* __restrict__ ze,
+                                   double* __restrict__ c) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= MN) return;
+  const int n = (int)(k % N);
+  c[k] = leb[4 * n + 3] * U[k] * (zr[k] + ze[k]);
+}
+// out += t at the active points (U > 0); inactive points keep their value
+__global__ void k_add_active(long MN, const double* __restrict__ U, const double* __restrict__ t,
+                             double* __restrict__ out) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= MN) return;
+  if (U[k] > 0.0) out[k] += t[k];
+}
 // y = a x + b y
 __global__ void k_axpby(long D, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
