@@ -167,6 +167,7 @@ struct ddlpb_ctx {
   double *d_f = nullptr, *d_U = nullptr;
   int *d_actcnt = nullptr, *d_actptr = nullptr, *d_actsph = nullptr, *d_actn = nullptr;
   double* d_pt4 = nullptr;
+  double *d_mu1 = nullptr, *d_mu2 = nullptr;
   double *d_ycr = nullptr, *d_yce = nullptr, *d_Cl = nullptr, *d_sgr = nullptr, *d_isgr = nullptr, *d_ur = nullptr, *d_iur = nullptr, *d_kr = nullptr;
   double *d_dtab = nullptr;
   double *d_rtab = nullptr;  // radius derivatives of the radial constants [4][M][LUR]
@@ -407,6 +408,8 @@ void carve(ddlpb_ctx* c, char* base, size_t* total) {
   c->d_dtab = cv.take<double>(3 * (size_t)c->L * c->LP);
   c->d_rtab = cv.take<double>(4 * (size_t)M * c->LUR);
   c->d_m = cv.take<double>(M * c->L);
+  c->d_mu1 = cv.take<double>(M * c->L);  // coefficient rows of the two-product stages
+  c->d_mu2 = cv.take<double>(M * c->L);
   c->d_lam = cv.take<double>(M * c->LP);
   c->d_psi = cv.take<double>(MN);
   c->d_e = cv.take<double>(MN);
@@ -645,8 +648,31 @@ void fill(ddlpb_ctx* c, double* p, long n, double v) {
   HIPCHK(hipGetLastError());
 }
 
+void gemm_f64(ddlpb_ctx* c, int R, int C, int K, const double* A, int lda, const double* B, int ldb,
+              const double* base, double c0, double* out, int ldo);
+// mu2 = An(U (.) Syn(mu1)) for every sphere: two matrix-core products through the
+// point-value scratch d_Vpt (free between the operator stages that use it)
+void syn_u_an(ddlpb_ctx* c) {
+  const long MN = (long)c->M * c->N;
+  gemm_f64(c, c->M, c->N, c->L, c->d_mu1, c->L, c->d_YT, c->N, nullptr, 0.0, c->d_Vpt, c->N);
+  hipLaunchKernelGGL(k_mul_grid, dim3(nblk(MN, 256)), dim3(256), 0, c->stream, MN, c->d_U, c->d_Vpt);
+  HIPCHK(hipGetLastError());
+  gemm_f64(c, c->M, c->L, c->N, c->d_Vpt, c->N, c->d_WY, c->L, nullptr, 0.0, c->d_mu2, c->L);
+}
 // m = C (.) An(U (.) (e + Syn(y(X))))
 void moments(ddlpb_ctx* c, const double* X, const double* egrid, double* h_out, double* m_out) {
+  if (X && !egrid && !h_out) {
+    // y(X) per degree, then the two products, then the C_l scaling
+    const long ML = (long)c->M * c->L;
+    hipLaunchKernelGGL(k_deg_scale, dim3(nblk(ML, 256)), dim3(256), 0, c->stream, c->M, c->L, c->LUR, c->d_ycr, X,
+                       c->d_yce, X + ML, c->L, c->d_mu1);
+    HIPCHK(hipGetLastError());
+    syn_u_an(c);
+    hipLaunchKernelGGL(k_deg_scale, dim3(nblk(ML, 256)), dim3(256), 0, c->stream, c->M, c->L, c->LUR, c->d_Cl,
+                       c->d_mu2, nullptr, nullptr, c->L, m_out);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   LM_DISPATCH(c->lmax, hipLaunchKernelGGL((k_moments<LMc>), dim3(c->M), dim3(256), 0, c->stream, c->M, c->N, c->LY,
                                           c->d_Y, c->d_leb, c->d_U, X, c->d_ycr, c->d_yce, c->LUR, egrid, c->d_Cl,
                                           h_out, m_out));
@@ -775,18 +801,14 @@ void apply_LTZ(ddlpb_ctx* c, const double* base, double c0, const double* zr, co
     }
     if (lam) {
       KScope ks(c, "sl_adjoint_part", 4.0 * c->N * c->L * (double)c->M);
-      // spheres per block: as many as fit 64 KB of LDS (at least one; 8 at 302 points)
-      const size_t per = (size_t)(c->L + c->N + 3 * c->L) * sizeof(double);
-      const int sb = (int)std::max<size_t>(1, std::min<size_t>(kLamSph, 65536 / per));
-      const size_t lds = per * sb;
-      LM_DISPATCH(c->lmax, {
-        if (lds > 65536)
-          HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lam_add<LMc>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((k_lam_add<LMc>), dim3((c->M + sb - 1) / sb), dim3(256), lds, c->stream, c->M, c->N,
-                           c->LY, sb, c->d_Y, c->d_YT, c->d_leb, c->d_U, c->d_ycr, c->d_yce, c->d_Cl, c->LUR, lam,
-                           llam, out);
-      });
+      // mu = An(U Syn(C_l lam)) by the two matrix-core products, then out += (ycr, yce) mu
+      const long ML = (long)c->M * c->L;
+      hipLaunchKernelGGL(k_deg_scale, dim3(nblk(ML, 256)), dim3(256), 0, c->stream, c->M, c->L, c->LUR, c->d_Cl, lam,
+                         nullptr, nullptr, llam, c->d_mu1);
+      HIPCHK(hipGetLastError());
+      syn_u_an(c);
+      hipLaunchKernelGGL(k_lam_out, dim3(nblk(ML, 256)), dim3(256), 0, c->stream, c->M, c->L, c->LUR, c->d_ycr,
+                         c->d_yce, c->d_mu2, out);
       HIPCHK(hipGetLastError());
     }
     return;

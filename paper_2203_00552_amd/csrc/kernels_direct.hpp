@@ -718,6 +718,32 @@ __global__ void k_mupdate(long D, int nv, const double* __restrict__ V, long ldv
   for (int v = 0; v < nv; ++v) s -= V[v * ldv + k] * h[v];
   w[k] = s;
 }
+// per-degree scaling of coefficient rows: out[j][t] = a[j][l] A[j][t] (+ b[j][l] B[j][t]),
+// l the degree of t; A (and B) with row stride lda, out with stride L
+__global__ void k_deg_scale(int M, int L, int LUR, const double* __restrict__ a, const double* __restrict__ A,
+                            const double* __restrict__ b, const double* __restrict__ B, int lda,
+                            double* __restrict__ out) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= (long)M * L) return;
+  const int j = (int)(k / L), t = (int)(k - (long)j * L), l = deg_of(t);
+  double v = a[j * LUR + l] * A[(long)j * lda + t];
+  if (b) v += b[j * LUR + l] * B[(long)j * lda + t];
+  out[k] = v;
+}
+// g *= U on the grid
+__global__ void k_mul_grid(long MN, const double* __restrict__ U, double* __restrict__ g) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k < MN) g[k] *= U[k];
+}
+// out_r[j][t] += ycr[j][l] mu[j][t], out_e[j][t] += yce[j][l] mu[j][t]
+__global__ void k_lam_out(int M, int L, int LUR, const double* __restrict__ ycr, const double* __restrict__ yce,
+                          const double* __restrict__ mu, double* __restrict__ out) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= (long)M * L) return;
+  const int j = (int)(k / L), t = (int)(k - (long)j * L), l = deg_of(t);
+  out[k] += ycr[j * LUR + l] * mu[k];
+  out[(long)M * L + k] += yce[j * LUR + l] * mu[k];
+}
 // adjoint grid charges from the two syntheses: c_in = w_n U_in (zr_in + ze_in)
 __global__ void k_charges_from_syn(long MN, int N, const double* __restrict__ leb, const double* __restrict__ U,
                                    const double* __restrict__ zr, const double* __restrict__ ze,
@@ -925,73 +951,6 @@ __global__ void k_point_sums(int M, int N, const int* __restrict__ pcp, const in
   Vpt[MN + idx] = c1 * b + cg * gE;
 }
 
-// The single-layer part of the transposed operator for the coefficients lam of every
-// sphere j: mu = An_j(U_j Syn(C_l lam_j)); out_r += ycr_l mu, out_e += yce_l mu.
-// One block of 256 threads takes sb <= kLamSph spheres, so the harmonic tables are read
-// once per sb spheres.  Dynamic LDS: sb (L + N) + 3 sb L doubles (three groups of
-// threads split the point sums when 3 L <= 256).
-constexpr int kLamSph = 8;
-template <int LM>
-__global__ __launch_bounds__(256) void k_lam_add(int M, int N, int LY, int sb, const double* __restrict__ Y,
-                                                 const double* __restrict__ YT, const double* __restrict__ leb,
-                                                 const double* __restrict__ U, const double* __restrict__ ycr,
-                                                 const double* __restrict__ yce, const double* __restrict__ Cl,
-                                                 int LUR, const double* __restrict__ lam, int LLAM,
-                                                 double* __restrict__ out) {
-  constexpr int L = (LM + 1) * (LM + 1);
-  constexpr int NG = 256 / L >= 3 ? 3 : (256 / L >= 1 ? 256 / L : 1);  // thread groups sharing the point sums
-  static_assert(L <= 256, "one thread per coefficient");
-  extern __shared__ double sh_raw[];
-  double* cl = sh_raw;                // [sb][L]
-  double* gg = cl + sb * L;           // [sb][N]
-  double* part = gg + (size_t)sb * N;  // [NG][sb][L]
-  const int j0 = blockIdx.x * sb, ns = min(sb, M - j0);
-  for (int u = threadIdx.x; u < sb * L; u += blockDim.x) {
-    const int s = u / L, t = u - s * L, j = j0 + s;
-    cl[u] = s < ns ? Cl[j * LUR + deg_of(t)] * lam[(long)j * LLAM + t] : 0.0;
-  }
-  __syncthreads();
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {  // Syn of the block's spheres at point n
-    double a[kLamSph];
-#pragma unroll
-    for (int s = 0; s < kLamSph; ++s) a[s] = 0.0;
-    for (int t = 0; t < L; ++t) {
-      const double y = YT[(long)t * N + n];
-#pragma unroll
-      for (int s = 0; s < kLamSph; ++s)
-        if (s < sb) a[s] += y * cl[s * L + t];
-    }
-#pragma unroll
-    for (int s = 0; s < kLamSph; ++s)
-      if (s < sb) gg[(size_t)s * N + n] = s < ns ? U[(long)(j0 + s) * N + n] * a[s] : 0.0;
-  }
-  __syncthreads();
-  const int g = threadIdx.x / L, t = threadIdx.x - g * L;  // An: group g sums its third of the points
-  if (g < NG) {
-    const int nper = (N + NG - 1) / NG, n0 = g * nper, n1 = min(N, n0 + nper);
-    double a[kLamSph];
-#pragma unroll
-    for (int s = 0; s < kLamSph; ++s) a[s] = 0.0;
-    for (int n = n0; n < n1; ++n) {
-      const double wy = leb[4 * n + 3] * Y[(long)n * LY + t];
-#pragma unroll
-      for (int s = 0; s < kLamSph; ++s)
-        if (s < sb) a[s] += wy * gg[(size_t)s * N + n];
-    }
-#pragma unroll
-    for (int s = 0; s < kLamSph; ++s)
-      if (s < sb) part[(g * sb + s) * L + t] = a[s];
-  }
-  __syncthreads();
-  for (int u = threadIdx.x; u < ns * L; u += blockDim.x) {
-    const int s = u / L, tt = u - s * L, j = j0 + s, l = deg_of(tt);
-    double mu = 0.0;
-#pragma unroll
-    for (int g2 = 0; g2 < NG; ++g2) mu += part[(g2 * sb + s) * L + tt];
-    out[(long)j * L + tt] += ycr[j * LUR + l] * mu;
-    out[(long)(M + j) * L + tt] += yce[j * LUR + l] * mu;
-  }
-}
 
 // ------------------------------------------- apply L (near part) from cap lists
 // Same result as k_apply_LX: one block per sphere i.  Each cap is evaluated by four
