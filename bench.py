@@ -212,7 +212,7 @@ def accuracy(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+        print(json.dumps({"error": "this benchmark runs on one GPU; runs on more than one GPU are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
@@ -273,7 +273,8 @@ def main():
     ctx.close()
     # roofline of the three kernels with the most device time (labels pass_* time whole FMM
     # passes, not one kernel); work = the library's count of algorithmic flops per launch
-    # (the design doc, section 8), time = HIP events on the context's stream
+    # (the flops of one translation, cap or pair times the units of the launch), time =
+    # HIP events on the context's stream
     fp32_labels = ("apply_LX", "apply_LTZ")  # cap-list kernels: one label for both precisions
     tops = sorted(((k, v) for k, v in kt.items() if not k.startswith("pass_")), key=lambda kv: -kv[1][0])[:3]
 
