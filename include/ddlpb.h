@@ -255,6 +255,10 @@ void ddlpb_free(ddlpb_ctx* ctx);
  *                    neighbour points inside each sphere) when they fit the
  *                    workspace estimate; 0: always the kernels that find the caps
  *                    on the fly from the neighbour lists (the fallback; FP64 only)
+ *   "inner_reorth"   1: the inner Krylov steps of the preconditioner (precond_krylov)
+ *                    re-orthogonalise their basis like the outer GMRES; 0 (default):
+ *                    one classical Gram-Schmidt pass (the outer flexible GMRES, which
+ *                    re-orthogonalises, absorbs the inexact preconditioner)
  *   "mixed_levels"   1: where the FP32-vector M2L runs (mixed_m2l, mixed_forces),
  *                    the order-12 screened Coulomb M2M/L2L level translations run
  *                    with the FP32 vector as well; 0 (default: they cost the mixed

@@ -116,6 +116,7 @@ struct ddlpb_ctx {
   bool sl32 = false;          // near single layer of the operator in FP32 (outer iterations of precision 1)
   int fp64_iters = 0;         // FP64 outer iterations after the FP32 ones in the last solve (precision 1)
   bool mixed_sl = false;
+  bool inner_reorth = false;  // option inner_reorth: second Gram-Schmidt pass in the inner Krylov steps
   bool m2l32 = false;         // screened Coulomb M2L with the FP32 vector (precision 1; level passes too with mixed_lvl)
   bool mixed_lvl = false;     // option mixed_levels: the order-12 level translations of the FP32 passes in FP32 too
   bool mixed_m2l = true;      // precision 1: outer iterations with the FP32-vector M2L (option mixed_m2l)
@@ -1337,12 +1338,13 @@ void axpby(ddlpb_ctx* c, double a, const double* x, double b, double* y) {
 using VecOp = std::function<void(const double*, double*)>;
 
 // Restarted right-preconditioned GMRES with classical Gram-Schmidt and one
-// re-orthogonalisation.  Flexible (FGMRES) when Z is given: the preconditioned
+// re-orthogonalisation (reorth; the short inner solves of the preconditioner may go
+// without it).  Flexible (FGMRES) when Z is given: the preconditioned
 // directions are stored, so the preconditioner may change between iterations.
 // Stops at ||b - A x|| <= tol ||b|| (or after maxit iterations / max_cycles cycles).
 int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b, double* x, double tol, int m,
                int maxit, int max_cycles, bool x_zero, double* V, double* Z, double* tw, double* tz, double* tc,
-               int* iters, double* relres) {
+               int* iters, double* relres, bool reorth = true) {
   const long D = 2L * c->M * c->L;
   const double bn = norm2(c, b);
   *iters = 0;
@@ -1378,8 +1380,12 @@ int gmres_core(ddlpb_ctx* c, const VecOp& op, const VecOp& prec, const double* b
       op(zj, w);
       mdot(c, j + 1, V, D, w, h.data());
       mupdate(c, j + 1, V, D, h.data(), w);
-      mdot(c, j + 1, V, D, w, h2.data());
-      mupdate(c, j + 1, V, D, h2.data(), w);
+      if (reorth) {
+        mdot(c, j + 1, V, D, w, h2.data());
+        mupdate(c, j + 1, V, D, h2.data(), w);
+      } else {
+        std::fill(h2.begin(), h2.end(), 0.0);
+      }
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
       const double hn = norm2(c, w);
       H[(size_t)(j + 1) * m + j] = hn;
@@ -1456,7 +1462,7 @@ int gmres(ddlpb_ctx* c, bool transpose, const double* b, double* x, double tol, 
       const int keep = c->cur_prec;
       if (fp32) c->cur_prec = 1;
       (void)gmres_core(c, opAB, jacp, in, out, 1e-30, c->pkrylov, c->pkrylov, 1, true, c->d_Vin, nullptr, c->d_t4,
-                       c->d_t1, c->d_t5, &it, &rr);
+                       c->d_t1, c->d_t5, &it, &rr, c->inner_reorth);
       c->cur_prec = keep;
       c->inner_total += it;
     };
@@ -2551,6 +2557,9 @@ int ddlpb_set_option(ddlpb_ctx* c, const char* key, double v) {
   } else if (k == "mixed_forces") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_forces = v != 0;
+  } else if (k == "inner_reorth") {
+    if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
+    c->inner_reorth = v != 0;
   } else if (k == "mixed_levels") {
     if (!(v == 0 || v == 1)) return DDLPB_EINVAL;
     c->mixed_lvl = v != 0;

@@ -111,7 +111,7 @@ def test_precision_and_kernel_options_are_validated():
     r = np.array([1.5, 1.5])
     q = np.array([0.5, -0.5])
     assert lib.ddlpb_setup(2, _lib.ptr(x), _lib.ptr(r), _lib.ptr(q), 1.0, 78.54, 0.104, 4, 110, 0, ctypes.byref(h)) == 0
-    for key in (b"mixed_m2l", b"mixed_forces", b"mixed_near_sl", b"mixed_levels", b"cap_lists"):
+    for key in (b"mixed_m2l", b"mixed_forces", b"mixed_near_sl", b"mixed_levels", b"cap_lists", b"inner_reorth"):
         assert lib.ddlpb_set_option(h, key, 0) == 0, key
         assert lib.ddlpb_set_option(h, key, 1) == 0, key
         assert lib.ddlpb_set_option(h, key, 2) == -1, key
